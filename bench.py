@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the limited-1PN direct N-body hot path on one MI355X.
+
+Default workload: Plummer sphere N = 16384 (16383 equal-mass stars, total
+star mass 1, scale radius 1, G = 1) plus a black hole of mass 0.05 at rest at
+the origin, c = 30, eps = 1e-4, FP64, fixed RK4 steps of dt = 1e-4.  One
+"step" is one RK4 step = 4 force evaluations (each: prologue, fused star-star
+sweep, epilogue with the Runge-Kutta stage update).  Inputs are resident on
+the GPU before the timed region.
+
+Metric: pair interactions per second = 4 * steps * N^2 / wall time.
+
+Printed (one JSON line on stdout): value, roofline of the fused pair kernel
+(its average duration measured live with HIP events on the stream it runs on),
+the CPU oracle timed on a bounded sample on this host, and a secondary
+N = 65536 mixed-precision vs FP64 comparison.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic flops per star-star pair interaction of the fused Newtonian +
+# 1PN sweep (add/sub/mul = 1, FMA = 2, rsqrt = 1; the Newton-type correction
+# of the FP64 reciprocal square root is overhead and not counted).
+FLOP_PER_PAIR_FUSED = 74.0
+PEAK_FP64_VALU = 78.6e12  # 256 CUs x 2.4 GHz x 64 FMA lanes x 2 flop
+PEAK_FP32_VALU_NONPACKED = 78.6e12  # same unit count: packed FP32 is not used
+# HBM traffic per fused-kernel launch from rocprofv3 PMC runs (FETCH_SIZE +
+# WRITE_SIZE, scaled by the copy-kernel calibration); None until measured for
+# the current kernel.
+TRAFFIC_BYTES = {}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="plummer_n16384_fp64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the N=65536 comparison")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1801_07986_amd as pn
+    from paper_1801_07986_amd import inputs
+
+    pn.load()
+    w = inputs.WORKLOADS[args.workload]
+    N, c, eps, dt = w["N"], w["c"], w["eps"], w["dt"]
+    prec = pn.PN_MIXED if w["precision"] == "mixed" else pn.PN_FP64
+    G = 1.0
+    log(f"workload {args.workload}: N={N} M_bh={w['M_bh']} c={c} eps={eps} dt={dt} "
+        f"precision={w['precision']} steps={args.steps} warmup={args.warmup}")
+    pos0, vel0, mass0 = inputs.plummer_bh(N, w["M_bh"], w["seed"])
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(pos0).to(dev)
+    vel = torch.from_numpy(vel0).to(dev)
+    mass = torch.from_numpy(mass0).to(dev)
+    stream = torch.cuda.current_stream()
+
+    # warmup (also captures the step graph)
+    pn.pn_step(pos, vel, mass, G, c, eps, dt, args.warmup, prec, stream=stream)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # timed region: exactly K steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pn.pn_step(pos, vel, mass, G, c, eps, dt, args.steps, prec, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    pairs = 4.0 * args.steps * float(N) * float(N)
+    value = pairs / wall
+    log(f"timed {args.steps} steps in {wall:.4f} s -> {value:.4e} pair/s")
+
+    # dominant kernel: the fused pair sweep, timed per launch with HIP events
+    # on the stream it runs on (direct launches, same kernels and shapes)
+    tsteps = max(2, min(25, args.steps))
+    pn.pn_step(pos, vel, mass, G, c, eps, dt, tsteps, prec, stream=stream, flags=pn.PN_TIMING)
+    tm = pn.pn_last_timing()
+    avg_s = tm["total_ms"] / tm["launches"] / 1e3
+    flops = FLOP_PER_PAIR_FUSED * tm["pairs_per_launch"]
+    achieved = flops / avg_s
+    peak = PEAK_FP64_VALU if prec == pn.PN_FP64 else PEAK_FP32_VALU_NONPACKED
+    kname = "k_pair<double,3,*>" if prec == pn.PN_FP64 else "k_pair<float,3,*>"
+    traffic = TRAFFIC_BYTES.get((args.workload, kname))
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                "kernel": kname, "avg_launch_ms": avg_s * 1e3, "launches": tm["launches"],
+                "flop_per_pair": FLOP_PER_PAIR_FUSED}
+    log(f"pair kernel avg {avg_s * 1e3:.4f} ms over {tm['launches']} launches -> "
+        f"{achieved / 1e12:.2f} TFLOP/s ({achieved / peak:.1%} of peak)")
+
+    result = {
+        "metric": "pair interactions/s (Newton+1PN)",
+        "value": value,
+        "unit": "pair/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == pn.PN_FP64 else "f32+f64",
+        "data": "synthetic (seeded Plummer sphere + black hole)",
+        "config": {"workload": args.workload, "N": N, "M_bh": w["M_bh"], "c": c, "eps": eps,
+                   "dt": dt, "integrator": "RK4", "precision": w["precision"],
+                   "evals_per_step": 4, "pairs_per_eval": "N^2"},
+        "roofline": roofline,
+    }
+
+    if not args.no_secondary:
+        result["secondary"] = secondary(pn, torch, inputs, stream)
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(pos0, vel0, mass0, G, c, eps)
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def secondary(pn, torch, inputs, stream):
+    """N = 65536 (M = 0.1, c = 30): mixed precision vs FP64, 10 RK4 steps each."""
+    w = inputs.WORKLOADS["plummer_n65536_mixed"]
+    N = w["N"]
+    pos0, vel0, mass0 = inputs.plummer_bh(N, w["M_bh"], w["seed"])
+    out = {"workload": "plummer_n65536", "N": N, "steps": 10}
+    for name, prec in (("mixed", pn.PN_MIXED), ("fp64", pn.PN_FP64)):
+        pos = torch.from_numpy(pos0).cuda()
+        vel = torch.from_numpy(vel0).cuda()
+        mass = torch.from_numpy(mass0).cuda()
+        pn.pn_step(pos, vel, mass, 1.0, w["c"], w["eps"], w["dt"], 1, prec, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pn.pn_step(pos, vel, mass, 1.0, w["c"], w["eps"], w["dt"], 10, prec, stream=stream)
+        torch.cuda.synchronize()
+        dt_wall = time.perf_counter() - t0
+        out[name + "_pair_per_s"] = 4.0 * 10 * N * N / dt_wall
+        log(f"secondary N={N} {name}: {out[name + '_pair_per_s']:.4e} pair/s")
+    out["mixed_over_fp64"] = out["mixed_pair_per_s"] / out["fp64_pair_per_s"]
+    return out
+
+
+def cpu_baseline(pos, vel, mass, G, c, eps, budget_s=12.0):
+    """The oracle (plain FP64 C, OpenMP over bodies) on this host's cores: full
+    force evaluations of the same workload, repeated until ~budget_s."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = oracle.max_threads()
+    N = len(mass)
+    n_eval, t_used = 0, 0.0
+    while t_used < budget_s and n_eval < 50:
+        t0 = time.perf_counter()
+        oracle.accel(pos, vel, mass, G, c, eps)
+        t_used += time.perf_counter() - t0
+        n_eval += 1
+        log(f"cpu oracle eval {n_eval}: {t_used:.2f} s")
+    return {"value": n_eval * float(N) * float(N) / t_used, "unit": "pair/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_eval} full force evaluation(s) of the N={N} workload "
+                      f"({t_used:.1f} s, {threads} OpenMP threads)"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

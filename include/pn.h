@@ -1,0 +1,155 @@
+/*
+ * pn.h -- C ABI of libpn, the MI355X (gfx950) implementation of the
+ * limited first-order post-Newtonian direct N-body hot path of
+ *   T. Tatekawa, "Accelerating N-body simulation of self-gravitating systems
+ *   with limited first-order post-Newtonian approximation" (arXiv:1801.07986).
+ *
+ * System: one massive object (the paper's body #1, here index 0, mass M) and
+ * N-1 low-mass stars (Sec. 2).  N counts the massive object.
+ *
+ * Common conventions for every entry point
+ * ----------------------------------------
+ * - Array arguments are DEVICE pointers (e.g. torch.Tensor.data_ptr() of a
+ *   CUDA/HIP tensor) to float64, C-contiguous, 8-byte aligned, unless marked
+ *   "host".  pos, vel, acc_*: [N][3] row-major (x, y, z of body b at
+ *   3b..3b+2); mass, phi: [N].  Inputs and outputs must not overlap, except
+ *   where stated.
+ * - Units are the caller's; G > 0.  c is the speed of light: lambda = 1/c^2
+ *   multiplies every 1PN term; c = +INFINITY is allowed and gives the
+ *   Newtonian equations exactly.
+ * - eps >= 0 is the Plummer softening length of Sec. 4, Eq. (10): every pair
+ *   distance r_ab (massive object included) is replaced by
+ *   R_ab = sqrt(r_ab^2 + eps^2) in every term, and n_ab = x_ab / R_ab.
+ * - stream: a hipStream_t, or NULL for the library's own stream (which, like
+ *   every default-flag stream, is ordered after the legacy default stream).
+ * - flags: 0 = synchronous: the call returns after the device work finished
+ *   and reports device-detected errors.  PN_ASYNC = enqueue only: returns after
+ *   launching; device-detected errors (PN_ENONFINITE, an invalid mass[0]) are
+ *   then not reported.
+ * - Ownership: the caller owns every argument buffer.  The library owns only
+ *   internal scratch, kept per device and grown on demand, and (pn_step) cached
+ *   HIP graphs; pn_release() frees both.  No argument pointer is kept after the
+ *   call returns, except inside pn_step's cached graph, which is re-captured
+ *   when any pointer or parameter changes.
+ * - Return codes: PN_OK, or one of the negative codes below.  No C++ exception
+ *   crosses the ABI.  Outputs are unspecified after an error, except
+ *   PN_ENONFINITE, where all outputs are written.
+ * - Determinism: identical inputs, sizes and schedule give bitwise-identical
+ *   outputs (fixed-order reductions, no floating-point atomics).
+ * - Thread safety: calls may come from several host threads; the library
+ *   serialises them internally.  Calls on one stream run in call order.
+ */
+#ifndef PN_H_
+#define PN_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PN_OK 0
+#define PN_EINVAL (-1)     /* bad argument (null/misaligned pointer, N < 2, G <= 0, c <= 0 or
+                              NaN, eps < 0, non-finite dt, nsteps < 0, unknown precision,
+                              mass[0] <= 0 detected on the device) */
+#define PN_ENONFINITE (-2) /* a non-finite acceleration was produced (outputs written) */
+#define PN_EDEVICE (-3)    /* HIP runtime error (text: pn_strerror(PN_EDEVICE)) */
+#define PN_ENOMEM (-4)     /* device allocation failed */
+
+/* precision of the O(N^2) star-star pair sums */
+#define PN_FP64 0  /* everything in FP64 */
+#define PN_MIXED 1 /* pair arithmetic in FP32 with FP64 coordinate differences and FP32
+                      partial sums carried in FP64 between j-tiles; black-hole terms,
+                      potentials, reductions and integrator state in FP64 */
+
+/* flags */
+#define PN_ASYNC 1   /* see above */
+#define PN_NOGRAPH 2 /* pn_step: launch kernels directly instead of replaying a graph */
+#define PN_TIMING 4  /* pn_step / pn_accel: time every pair-kernel launch with HIP events
+                        (implies PN_NOGRAPH); read with pn_last_timing() */
+
+/*
+ * Newtonian acceleration and potential of all N bodies: the first terms of
+ * Eq. (1) (massive object) and Eq. (4) (stars; printed with r_ij where r_ij^3
+ * is meant), softened per Eq. (10):
+ *   acc_newton[a] = -sum_{b != a} G m_b x_ab / R_ab^3,
+ *   phi[a]        = -sum_{b != a} G m_b / R_ab.
+ * vel and c are not used (kept so every call takes the same system
+ * description); vel may be NULL.  c must still be valid.
+ */
+int pn_potential_accel(const double* pos, const double* vel, const double* mass, int64_t N,
+                       double G, double c, double eps, double* acc_newton, double* phi,
+                       void* stream, int flags);
+
+/*
+ * Limited-1PN acceleration of all N bodies, lambda times the bracketed terms of
+ * Eqs. (1)-(6): Eqs. (2)+(3) for the massive object, (5)+(6) for the stars.
+ * phi and acc_newton are the Newtonian potential and acceleration of all bodies
+ * at the same positions (normally pn_potential_accel's outputs); they supply
+ * the potentials and Newtonian accelerations inside the 1PN brackets.  The
+ * massive object's own velocity vel[0] is not used: Eqs. (2)-(6) contain no
+ * v_1; its linear occurrences in the underlying EIH equations appear through
+ * w = -sum_s m_s v_s / M (second and sixth lines of Eq. (6), last line of
+ * Eq. (3)).  Output acc_1pn: [N][3]; total acceleration = acc_newton + acc_1pn.
+ */
+int pn_correction(const double* pos, const double* vel, const double* mass, int64_t N,
+                  double G, double c, double eps, const double* phi, const double* acc_newton,
+                  double* acc_1pn, void* stream, int flags);
+
+/*
+ * One full force evaluation as pn_step performs it (one fused star-star
+ * sweep in the given precision): Newtonian acceleration, potential and 1PN
+ * part of all N bodies.  Any of the three outputs may be NULL.
+ */
+int pn_accel(const double* pos, const double* vel, const double* mass, int64_t N, double G,
+             double c, double eps, int precision, double* acc_newton, double* phi,
+             double* acc_1pn, void* stream, int flags);
+
+/*
+ * Advance (pos, vel) of all N bodies, massive object included, by nsteps
+ * fixed steps of the classical fourth-order Runge-Kutta method (Sec. 3.2 and
+ * Sec. 4): four force evaluations per step, f(x, v) = (v, a^N + a^1PN).
+ * pos and vel are read and overwritten in place; mass is read only.
+ * nsteps = 0 is a no-op.  precision: PN_FP64 or PN_MIXED.
+ */
+int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, double c,
+            double eps, double dt, int64_t nsteps, int precision, void* stream, int flags);
+
+/*
+ * Conserved quantities of Sec. 2: 1PN total energy (Eq. (7)) and momentum
+ * (Eq. (8)), by the sum conventions of those equations (ordered star pairs
+ * i != j where r_ij appears; the last sum of Eq. (7) includes i = j).
+ * out8 (HOST pointer, 8 doubles): [E_N, lambda*E_1PN, P_N(3), lambda*P_1PN(3)],
+ * E = out8[0] + out8[1], P = out8[2..4] + out8[5..7].
+ */
+int pn_diagnostics(const double* pos, const double* vel, const double* mass, int64_t N,
+                   double G, double c, double eps, double* out8, void* stream, int flags);
+
+/*
+ * Many independent systems advanced together (each as pn_step would).
+ * System b occupies bodies offsets[b] .. offsets[b+1]-1 of the concatenated
+ * pos/vel/mass arrays, its massive object at offsets[b]; offsets (HOST, n_sys+1
+ * entries) starts at 0 and increases by at least 2 per system.  G, c, eps
+ * (HOST, n_sys entries each) are per-system parameters; dt is common.
+ */
+int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, const double* c,
+                    const double* eps, double* pos, double* vel, const double* mass, double dt,
+                    int64_t nsteps, int precision, void* stream, int flags);
+
+/* Text for a return code (PN_EDEVICE: the last HIP error seen).  Never NULL. */
+const char* pn_strerror(int code);
+
+/*
+ * After a call made with PN_TIMING: out (HOST, 3 doubles) receives
+ * [number of pair-kernel launches, their total duration in ms, pairs per launch].
+ */
+int pn_last_timing(double* out);
+
+/* Frees the library's scratch memory and cached graphs on every device. */
+int pn_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PN_H_ */

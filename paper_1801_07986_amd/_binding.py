@@ -1,0 +1,147 @@
+"""ctypes binding of libpn (include/pn.h): argument marshalling only.
+
+Every function takes torch tensors on the GPU (float64, contiguous) and
+passes their device pointers to the C ABI; all arithmetic runs in the HIP
+kernels.  The library must have been built (``python -m
+paper_1801_07986_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpn.so")
+
+PN_OK, PN_EINVAL, PN_ENONFINITE, PN_EDEVICE, PN_ENOMEM = 0, -1, -2, -3, -4
+PN_FP64, PN_MIXED = 0, 1
+PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
+
+EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
+           "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release")
+
+
+class PNError(RuntimeError):
+    def __init__(self, code: int, name: str, text: str):
+        super().__init__(f"{name} failed with code {code}: {text}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libpn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              f"`python -m paper_1801_07986_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, d, i64, i32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int
+        lib.pn_potential_accel.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, i32]
+        lib.pn_correction.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, vp, i32]
+        lib.pn_accel.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
+        lib.pn_step.argtypes = [vp, vp, vp, i64, d, d, d, d, i64, i32, vp, i32]
+        lib.pn_diagnostics.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, i32]
+        lib.pn_step_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, d, i64, i32,
+                                        vp, i32]
+        lib.pn_strerror.argtypes = [i32]
+        lib.pn_strerror.restype = ctypes.c_char_p
+        lib.pn_last_timing.argtypes = [vp]
+        lib.pn_release.argtypes = []
+        for name in EXPORTS:
+            if name != "pn_strerror":
+                getattr(lib, name).restype = i32
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, name: str) -> int:
+    if rc != PN_OK:
+        raise PNError(rc, name, load().pn_strerror(rc).decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() \
+            or t.device.type != "cuda":
+        raise TypeError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(int(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream))
+
+
+def _n(mass) -> int:
+    return int(mass.shape[0])
+
+
+def pn_potential_accel(pos, vel, mass, G, c, eps, acc_newton, phi, stream=None, flags=0):
+    return _check(load().pn_potential_accel(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
+                                            _ptr(acc_newton), _ptr(phi), _stream(stream), flags),
+                  "pn_potential_accel")
+
+
+def pn_correction(pos, vel, mass, G, c, eps, phi, acc_newton, acc_1pn, stream=None, flags=0):
+    return _check(load().pn_correction(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
+                                       _ptr(phi), _ptr(acc_newton), _ptr(acc_1pn),
+                                       _stream(stream), flags), "pn_correction")
+
+
+def pn_accel(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None, acc_1pn=None,
+             stream=None, flags=0):
+    return _check(load().pn_accel(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
+                                  precision, _ptr(acc_newton), _ptr(phi), _ptr(acc_1pn),
+                                  _stream(stream), flags), "pn_accel")
+
+
+def pn_step(pos, vel, mass, G, c, eps, dt, nsteps, precision=PN_FP64, stream=None, flags=0):
+    return _check(load().pn_step(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps, dt,
+                                 int(nsteps), precision, _stream(stream), flags), "pn_step")
+
+
+def pn_diagnostics(pos, vel, mass, G, c, eps, stream=None, flags=0):
+    out = (ctypes.c_double * 8)()
+    _check(load().pn_diagnostics(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
+                                 ctypes.cast(out, ctypes.c_void_p), _stream(stream), flags),
+           "pn_diagnostics")
+    return list(out)
+
+
+def pn_step_batched(offsets, G, c, eps, pos, vel, mass, dt, nsteps, precision=PN_FP64,
+                    stream=None, flags=0):
+    n_sys = len(offsets) - 1
+    off = (ctypes.c_int64 * (n_sys + 1))(*[int(o) for o in offsets])
+    g = (ctypes.c_double * n_sys)(*[float(x) for x in G])
+    cc = (ctypes.c_double * n_sys)(*[float(x) for x in c])
+    ee = (ctypes.c_double * n_sys)(*[float(x) for x in eps])
+    cast = lambda a: ctypes.cast(a, ctypes.c_void_p)  # noqa: E731
+    return _check(load().pn_step_batched(n_sys, cast(off), cast(g), cast(cc), cast(ee), _ptr(pos),
+                                         _ptr(vel), _ptr(mass), dt, int(nsteps), precision,
+                                         _stream(stream), flags), "pn_step_batched")
+
+
+def pn_last_timing():
+    out = (ctypes.c_double * 3)()
+    _check(load().pn_last_timing(ctypes.cast(out, ctypes.c_void_p)), "pn_last_timing")
+    return {"launches": int(out[0]), "total_ms": out[1], "pairs_per_launch": out[2]}
+
+
+def pn_release():
+    return _check(load().pn_release(), "pn_release")
+
+
+def pn_strerror(code: int) -> str:
+    return load().pn_strerror(code).decode()
+
+
+INF = math.inf

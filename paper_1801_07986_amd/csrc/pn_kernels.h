@@ -1,0 +1,741 @@
+// pn_kernels.h -- gfx950 device code of libpn (included once, by pn_api.hip).
+//
+// Notation (Sec. 2 of the paper): body 0 is the massive object (the paper's
+// #1, mass M); stars are bodies 1..N-1, stored as "star k" = body k+1 in every
+// star-indexed array (Ns = N-1 stars).  x_ab = x_a - x_b, R_ab = sqrt(r^2+eps^2)
+// (Eq. (10)), lambda = 1/c^2.
+//
+// Per force evaluation the work is split into
+//   k_prologue   O(N)   massive-object/star pair terms u_s = G M / R_s0 and
+//                       b_s = G M x_s0 / R_s0^3, star packets for the pair
+//                       sweep, block partials of sum m_s b_s, m_s u_s, m_s v_s;
+//   k_pair       O(N^2) star-star sweep: per star i the sums
+//                         U_i  = sum_j G m_j / R_ij                (potential)
+//                         G_i  = sum_j G m_j x_ij / R_ij^3         (= -g_i)
+//                         Q_i  = sum_j (G m_j/R^3)[S'_ij x_ij - D'_ij v_j]
+//                         C2_i = sum_j (G m_j/R^3) D'_ij
+//                         Q7_i = sum_j (G m_j/R) (-b_j / 2)
+//                       with S'_ij = e_j + 4 v_i.v_j + 3/2 (x_ij.v_j/R)^2
+//                       - x_ij.b_j/2, e_j = -2 v_j^2 + u_j, and
+//                       D'_ij = x_ij.(4 v_i - 3 v_j); written per j-split;
+//   k_epilogue   O(N)   per star: reduces the splits, assembles the Newtonian
+//                       and 1PN accelerations (Eqs. (4)-(6)), the star's term
+//                       of the massive object's 1PN sum (Eqs. (2)-(3)) as block
+//                       partials, and the Runge-Kutta stage update;
+//   k_bh_final   O(N)   one block: the massive object's acceleration (Eq. (1))
+//                       and stage update.
+// The star-star 1PN sum of Eq. (6) needs no pass-1 result of any other star
+// (only x, v, m and the O(N) massive-object terms u_j, b_j), so the potential
+// sweep and the 1PN sweep share one pass over j.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pn {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+constexpr int kNF = 11;      // pair-sum fields: U, G(3), Q(3), C2, Q7(3)
+enum Field { F_U = 0, F_G = 1, F_Q = 4, F_C2 = 7, F_Q7 = 8 };
+enum PairMode { MODE_P1 = 1, MODE_P2 = 2, MODE_FUSED = 3 };
+
+// Star packet read by the pair sweep.  Positions stay FP64 so that coordinate
+// differences are formed in FP64 in both precisions.
+struct alignas(16) PkF64 {
+  double x, y, z, gm, vx, vy, vz, e, hbx, hby, hbz, pad;
+};
+struct alignas(16) PkF32 {
+  double x, y, z;
+  float gm, vx, vy, vz, e, hbx, hby, hbz, pad0, pad1;
+};
+static_assert(sizeof(PkF64) == 96, "packet layout");
+static_assert(sizeof(PkF32) == 64, "packet layout");
+
+template <typename T> struct PkOf;
+template <> struct PkOf<double> { using type = PkF64; };
+template <> struct PkOf<float> { using type = PkF32; };
+
+// ---------------------------------------------------------------------------
+// Reciprocal square root in FP64.  The hardware estimate (v_rsq_f64) is good
+// to about 2^-24 relative; one step of the third-order series
+//   1/sqrt(x) = y (1 - r)^(-1/2) = y (1 + r/2 + 3 r^2/8 + ...),  r = 1 - x y^2
+// brings it to full double precision (residual ~ (5/16) r^3 < 2^-70).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double r = fma(-x * y, y, 1.0);
+  double p = fma(0.375, r, 0.5);
+  return fma(y * r, p, y);
+}
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt_f64(x); }
+
+// Fixed-order workgroup sum of K doubles per thread; result in lds[k*kBlock].
+template <int K>
+__device__ __forceinline__ void block_sum(const double (&v)[K], double* lds) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) lds[k * kBlock + t] = v[k];
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) lds[k * kBlock + t] += lds[k * kBlock + t + s];
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of `rows` partial rows of width `stride` (first K columns), fixed order:
+// thread t sums rows t, t+kBlock, ..., then a tree.  Same result in every block.
+template <int K>
+__device__ __forceinline__ void reduce_rows(const double* part, int rows, int stride,
+                                            double* lds, double (&out)[K]) {
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int r = threadIdx.x; r < rows; r += kBlock) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += part[(size_t)r * stride + k];
+  }
+  block_sum<K>(v, lds);
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = lds[k * kBlock];
+  __syncthreads();
+}
+
+__global__ void k_reset_status(int* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) status[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Prologue: massive-object/star pair terms and star packets (O(N), FP64).
+// ---------------------------------------------------------------------------
+struct ProArgs {
+  const double* pos;  // [N][3] (state of this evaluation)
+  const double* vel;  // [N][3] or nullptr (Newtonian-only evaluation)
+  const double* mass; // [N]
+  int Ns;
+  double G, eps2;
+  void* pk;       // [Ns] PkF64 or PkF32
+  double* ub;     // [Ns][4]: u_s, b_s(3)
+  double* bpart;  // [gridDim.x][8]: sum m b (3), sum m u, sum m v (3), 0
+  int* status;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
+  __shared__ double lds[7 * kBlock];
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (k < a.Ns) {
+    const int s = k + 1;
+    const double x0 = a.pos[0], y0 = a.pos[1], z0 = a.pos[2];
+    const double xs = a.pos[3 * s], ys = a.pos[3 * s + 1], zs = a.pos[3 * s + 2];
+    const double dx = xs - x0, dy = ys - y0, dz = zs - z0;
+    const double rinv = rsqrt_f64(fma(dz, dz, fma(dy, dy, fma(dx, dx, a.eps2))));
+    const double gM = a.G * a.mass[0];
+    const double u = gM * rinv;
+    const double b3 = u * rinv * rinv;
+    const double bx = b3 * dx, by = b3 * dy, bz = b3 * dz;
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (a.vel) {
+      vx = a.vel[3 * s];
+      vy = a.vel[3 * s + 1];
+      vz = a.vel[3 * s + 2];
+    }
+    const double v2 = fma(vz, vz, fma(vy, vy, vx * vx));
+    const double m = a.mass[s];
+    using Pk = typename PkOf<T>::type;
+    Pk p;
+    p.x = xs;
+    p.y = ys;
+    p.z = zs;
+    p.gm = (T)(a.G * m);
+    p.vx = (T)vx;
+    p.vy = (T)vy;
+    p.vz = (T)vz;
+    p.e = (T)fma(-2.0, v2, u);
+    p.hbx = (T)(-0.5 * bx);
+    p.hby = (T)(-0.5 * by);
+    p.hbz = (T)(-0.5 * bz);
+    if constexpr (sizeof(T) == 8) {
+      p.pad = 0.0;
+    } else {
+      p.pad0 = 0.f;
+      p.pad1 = 0.f;
+    }
+    static_cast<Pk*>(a.pk)[k] = p;
+    double* ub = a.ub + 4 * (size_t)k;
+    ub[0] = u;
+    ub[1] = bx;
+    ub[2] = by;
+    ub[3] = bz;
+    v[0] = m * bx;
+    v[1] = m * by;
+    v[2] = m * bz;
+    v[3] = m * u;
+    v[4] = m * vx;
+    v[5] = m * vy;
+    v[6] = m * vz;
+  }
+  block_sum<7>(v, lds);
+  if (threadIdx.x < 8) {
+    a.bpart[(size_t)blockIdx.x * 8 + threadIdx.x] = threadIdx.x < 7 ? lds[threadIdx.x * kBlock] : 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double M = a.mass[0];
+    if (!(M > 0.0) || !isfinite(M)) atomicOr(a.status, 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Star-star sweep.  i-bodies live in registers (IPT per thread); every lane of
+// a wavefront visits the same j at the same time, so the j packet is uniform
+// and is read through the scalar unit into SGPRs (no LDS traffic, no
+// per-lane broadcast).  The j range of a workgroup is one of gridDim.y
+// splits; partial sums go to part[split][field][star].
+// T = double: FP64 throughout.  T = float: FP64 coordinate differences, FP32
+// pair arithmetic, FP32 partial sums over tiles of kTile j, added into FP64
+// accumulators after each tile.
+// ---------------------------------------------------------------------------
+struct PairArgs {
+  const void* pk;
+  int Ns;
+  int jchunk;  // j per split
+  double eps2;
+  double* part;  // [gridDim.y][kNF][Ns]
+};
+
+constexpr int kTile = 64;  // j per FP32 partial-sum tile (mixed precision)
+
+template <typename T, int MODE, int IPT>
+struct PairAcc {
+  T U[IPT], Gx[IPT], Gy[IPT], Gz[IPT], Qx[IPT], Qy[IPT], Qz[IPT], C2[IPT], Q7x[IPT], Q7y[IPT],
+      Q7z[IPT];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      U[i] = Gx[i] = Gy[i] = Gz[i] = Qx[i] = Qy[i] = Qz[i] = C2[i] = Q7x[i] = Q7y[i] = Q7z[i] = T(0);
+    }
+  }
+};
+
+template <typename T, int MODE, int IPT, bool MASK>
+__device__ __forceinline__ void pair_range(const typename PkOf<T>::type* __restrict__ pk, int j0,
+                                           int j1, T eps2, const double (&xi)[IPT],
+                                           const double (&yi)[IPT], const double (&zi)[IPT],
+                                           const T (&v4x)[IPT], const T (&v4y)[IPT],
+                                           const T (&v4z)[IPT], const int (&idx)[IPT],
+                                           PairAcc<T, MODE, IPT>& A) {
+#pragma unroll 2
+  for (int j = j0; j < j1; ++j) {
+    const auto& p = pk[j];
+    const double xj = p.x, yj = p.y, zj = p.z;
+    const T gm = p.gm;
+#pragma unroll
+    for (int ii = 0; ii < IPT; ++ii) {
+      const T dx = (T)(xi[ii] - xj), dy = (T)(yi[ii] - yj), dz = (T)(zi[ii] - zj);
+      T rinv = rsqrt_t(fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2))));
+      if (MASK) rinv = (j == idx[ii]) ? T(0) : rinv;
+      const T rinv2 = rinv * rinv;
+      const T mr = gm * rinv;
+      const T mr3 = mr * rinv2;
+      if (MODE & MODE_P1) A.U[ii] += mr;
+      A.Gx[ii] = fma(mr3, dx, A.Gx[ii]);
+      A.Gy[ii] = fma(mr3, dy, A.Gy[ii]);
+      A.Gz[ii] = fma(mr3, dz, A.Gz[ii]);
+      if (MODE & MODE_P2) {
+        const T vxj = p.vx, vyj = p.vy, vzj = p.vz;
+        const T xvj = fma(dz, vzj, fma(dy, vyj, dx * vxj));
+        const T x4vi = fma(dz, v4z[ii], fma(dy, v4y[ii], dx * v4x[ii]));
+        T s = fma(v4z[ii], vzj, fma(v4y[ii], vyj, fma(v4x[ii], vxj, (T)p.e)));
+        s = fma(dz, (T)p.hbz, fma(dy, (T)p.hby, fma(dx, (T)p.hbx, s)));
+        const T t = xvj * rinv;
+        s = fma(T(1.5) * t, t, s);
+        const T D = fma(T(-3), xvj, x4vi);
+        const T c1 = mr3 * s, c2 = mr3 * D;
+        A.Qx[ii] = fma(-c2, vxj, fma(c1, dx, A.Qx[ii]));
+        A.Qy[ii] = fma(-c2, vyj, fma(c1, dy, A.Qy[ii]));
+        A.Qz[ii] = fma(-c2, vzj, fma(c1, dz, A.Qz[ii]));
+        A.C2[ii] += c2;
+        A.Q7x[ii] = fma(mr, (T)p.hbx, A.Q7x[ii]);
+        A.Q7y[ii] = fma(mr, (T)p.hby, A.Q7y[ii]);
+        A.Q7z[ii] = fma(mr, (T)p.hbz, A.Q7z[ii]);
+      }
+    }
+  }
+}
+
+template <typename T, int MODE, int IPT>
+__device__ __forceinline__ void pair_segment(const typename PkOf<T>::type* __restrict__ pk, int j0,
+                                             int j1, int ilo, int ihi, T eps2,
+                                             const double (&xi)[IPT], const double (&yi)[IPT],
+                                             const double (&zi)[IPT], const T (&v4x)[IPT],
+                                             const T (&v4y)[IPT], const T (&v4z)[IPT],
+                                             const int (&idx)[IPT], PairAcc<T, MODE, IPT>& A) {
+  // the diagonal j == i can only occur for j in [ilo, ihi)
+  const int m0 = max(j0, ilo), m1 = min(j1, ihi);
+  if (m0 < m1) {
+    pair_range<T, MODE, IPT, false>(pk, j0, m0, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
+    pair_range<T, MODE, IPT, true>(pk, m0, m1, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
+    pair_range<T, MODE, IPT, false>(pk, m1, j1, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
+  } else {
+    pair_range<T, MODE, IPT, false>(pk, j0, j1, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
+  }
+}
+
+template <typename T, int MODE, int IPT>
+__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
+  using Pk = typename PkOf<T>::type;
+  const Pk* __restrict__ pk = static_cast<const Pk*>(a.pk);
+  const int ilo = blockIdx.x * (kBlock * IPT);
+  const int ihi = min(a.Ns, ilo + kBlock * IPT);
+  double xi[IPT], yi[IPT], zi[IPT];
+  T v4x[IPT], v4y[IPT], v4z[IPT];
+  int idx[IPT];
+#pragma unroll
+  for (int ii = 0; ii < IPT; ++ii) {
+    idx[ii] = ilo + threadIdx.x + ii * kBlock;
+    const int il = min(idx[ii], a.Ns - 1);  // lanes past the end compute on a copy, never stored
+    const Pk& p = pk[il];
+    xi[ii] = p.x;
+    yi[ii] = p.y;
+    zi[ii] = p.z;
+    v4x[ii] = T(4) * (T)p.vx;
+    v4y[ii] = T(4) * (T)p.vy;
+    v4z[ii] = T(4) * (T)p.vz;
+  }
+  const int split = blockIdx.y;
+  const int j0 = split * a.jchunk;
+  const int j1 = min(a.Ns, j0 + a.jchunk);
+  const T eps2 = (T)a.eps2;
+
+  double acc[kNF][IPT];
+#pragma unroll
+  for (int f = 0; f < kNF; ++f)
+#pragma unroll
+    for (int ii = 0; ii < IPT; ++ii) acc[f][ii] = 0.0;
+
+  PairAcc<T, MODE, IPT> A;
+  if constexpr (sizeof(T) == 8) {
+    A.zero();
+    pair_segment<T, MODE, IPT>(pk, j0, j1, ilo, ihi, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
+#pragma unroll
+    for (int ii = 0; ii < IPT; ++ii) {
+      acc[F_U][ii] = A.U[ii];
+      acc[F_G][ii] = A.Gx[ii];
+      acc[F_G + 1][ii] = A.Gy[ii];
+      acc[F_G + 2][ii] = A.Gz[ii];
+      acc[F_Q][ii] = A.Qx[ii];
+      acc[F_Q + 1][ii] = A.Qy[ii];
+      acc[F_Q + 2][ii] = A.Qz[ii];
+      acc[F_C2][ii] = A.C2[ii];
+      acc[F_Q7][ii] = A.Q7x[ii];
+      acc[F_Q7 + 1][ii] = A.Q7y[ii];
+      acc[F_Q7 + 2][ii] = A.Q7z[ii];
+    }
+  } else {
+    for (int t0 = j0; t0 < j1; t0 += kTile) {
+      const int t1 = min(j1, t0 + kTile);
+      A.zero();
+      pair_segment<T, MODE, IPT>(pk, t0, t1, ilo, ihi, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
+#pragma unroll
+      for (int ii = 0; ii < IPT; ++ii) {
+        acc[F_U][ii] += (double)A.U[ii];
+        acc[F_G][ii] += (double)A.Gx[ii];
+        acc[F_G + 1][ii] += (double)A.Gy[ii];
+        acc[F_G + 2][ii] += (double)A.Gz[ii];
+        if (MODE & MODE_P2) {
+          acc[F_Q][ii] += (double)A.Qx[ii];
+          acc[F_Q + 1][ii] += (double)A.Qy[ii];
+          acc[F_Q + 2][ii] += (double)A.Qz[ii];
+          acc[F_C2][ii] += (double)A.C2[ii];
+          acc[F_Q7][ii] += (double)A.Q7x[ii];
+          acc[F_Q7 + 1][ii] += (double)A.Q7y[ii];
+          acc[F_Q7 + 2][ii] += (double)A.Q7z[ii];
+        }
+      }
+    }
+  }
+
+  const size_t plane = (size_t)a.Ns;
+  double* out = a.part + (size_t)split * kNF * plane;
+#pragma unroll
+  for (int ii = 0; ii < IPT; ++ii) {
+    if (idx[ii] < a.Ns) {
+      if (MODE & MODE_P1) out[F_U * plane + idx[ii]] = acc[F_U][ii];
+      out[(F_G + 0) * plane + idx[ii]] = acc[F_G][ii];
+      out[(F_G + 1) * plane + idx[ii]] = acc[F_G + 1][ii];
+      out[(F_G + 2) * plane + idx[ii]] = acc[F_G + 2][ii];
+      if (MODE & MODE_P2) {
+#pragma unroll
+        for (int f = F_Q; f < kNF; ++f) out[f * plane + idx[ii]] = acc[f][ii];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue (per star) and final step (massive object).
+// ---------------------------------------------------------------------------
+struct EpiArgs {
+  const double* pos;  // [N][3] state of this evaluation
+  const double* vel;  // [N][3] (may be nullptr when newton_only)
+  const double* mass;
+  int Ns;
+  double G, lam, eps2;
+  const double* ub;     // [Ns][4]
+  const double* bpart;  // prologue partials [nbpro][8]
+  int nbpro;
+  const double* part;  // pair partials [nsplit][kNF][Ns]
+  int nsplit;
+  int newton_only;      // skip every 1PN term
+  const double* phi_in; // correction mode: Newtonian potential of all N bodies (else nullptr)
+  const double* accN_in;// correction mode: Newtonian acceleration of all N bodies
+  double* acc_newton;   // outputs, [N][3] / [N] (any may be nullptr)
+  double* phi;
+  double* acc_1pn;
+  double* bhpart;  // [gridDim.x][4]: the massive object's 1PN sum, block partials
+  int nbepi;       // (k_bh_final) number of bhpart rows
+  int* status;
+  // Runge-Kutta stage update (stage < 0: none)
+  int stage;
+  double dt;
+  double *X, *V, *Xs, *Vs, *KX, *KV;  // [N][3]
+};
+
+// Classical RK4 bookkeeping for one body component.  The evaluation state of
+// stage 0 is (X, V); of stages 1-3 it is (Xs, Vs).  KX/KV accumulate
+// k1 + 2 k2 + 2 k3; stage 3 applies y += dt/6 (k1 + 2 k2 + 2 k3 + k4).
+__device__ __forceinline__ void rk4_update(const EpiArgs& a, size_t o, double xv, double acc) {
+  // xv: velocity of the evaluation state (the position derivative k_x)
+  switch (a.stage) {
+    case 0:
+      a.KX[o] = xv;
+      a.KV[o] = acc;
+      a.Xs[o] = a.X[o] + 0.5 * a.dt * xv;
+      a.Vs[o] = a.V[o] + 0.5 * a.dt * acc;
+      break;
+    case 1:
+      a.KX[o] = a.KX[o] + 2.0 * xv;
+      a.KV[o] = a.KV[o] + 2.0 * acc;
+      a.Xs[o] = a.X[o] + 0.5 * a.dt * xv;
+      a.Vs[o] = a.V[o] + 0.5 * a.dt * acc;
+      break;
+    case 2:
+      a.KX[o] = a.KX[o] + 2.0 * xv;
+      a.KV[o] = a.KV[o] + 2.0 * acc;
+      a.Xs[o] = a.X[o] + a.dt * xv;
+      a.Vs[o] = a.V[o] + a.dt * acc;
+      break;
+    case 3:
+      a.X[o] = a.X[o] + a.dt / 6.0 * (a.KX[o] + xv);
+      a.V[o] = a.V[o] + a.dt / 6.0 * (a.KV[o] + acc);
+      break;
+    default:
+      break;
+  }
+}
+
+// The massive object's acceleration A0 = a^N_0, potential magnitude V0 = -phi_0
+// and the star momentum P, from the prologue partials (or the caller's inputs).
+__device__ __forceinline__ void bh_quantities(const EpiArgs& a, double* lds, double (&A0)[3],
+                                              double& V0, double (&P)[3]) {
+  double r[7];
+  reduce_rows<7>(a.bpart, a.nbpro, 8, lds, r);
+  const double M = a.mass[0];
+  A0[0] = r[0] / M;
+  A0[1] = r[1] / M;
+  A0[2] = r[2] / M;
+  V0 = r[3] / M;
+  P[0] = r[4];
+  P[1] = r[5];
+  P[2] = r[6];
+  if (a.phi_in) {
+    V0 = -a.phi_in[0];
+    A0[0] = a.accN_in[0];
+    A0[1] = a.accN_in[1];
+    A0[2] = a.accN_in[2];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
+  __shared__ double lds[7 * kBlock];
+  double A0[3], V0, P[3];
+  bh_quantities(a, lds, A0, V0, P);
+  const double M = a.mass[0];
+  const double gM = a.G * M;
+  const double w[3] = {-P[0] / M, -P[1] / M, -P[2] / M};
+  const double x0 = a.pos[0], y0 = a.pos[1], z0 = a.pos[2];
+
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  double bh[3] = {0.0, 0.0, 0.0};
+  if (k < a.Ns) {
+    const int i = k + 1;
+    const size_t plane = (size_t)a.Ns;
+    double sum[kNF];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f) sum[f] = 0.0;
+    for (int sp = 0; sp < a.nsplit; ++sp) {
+      const double* pp = a.part + (size_t)sp * kNF * plane + k;
+      if (!a.phi_in) sum[F_U] += pp[F_U * plane];  // not computed in correction mode
+      sum[F_G] += pp[F_G * plane];
+      sum[F_G + 1] += pp[(F_G + 1) * plane];
+      sum[F_G + 2] += pp[(F_G + 2) * plane];
+      if (!a.newton_only) {
+#pragma unroll
+        for (int f = F_Q; f < kNF; ++f) sum[f] += pp[f * plane];
+      }
+    }
+    const double* ub = a.ub + 4 * (size_t)k;
+    const double ui = ub[0], bx = ub[1], by = ub[2], bz = ub[3];
+    // Newtonian part: g_i - b_i with g_i = -G_i
+    const double aN[3] = {-sum[F_G] - bx, -sum[F_G + 1] - by, -sum[F_G + 2] - bz};
+    double Vi = sum[F_U] + ui;  // -phi_i
+    double a1[3] = {0.0, 0.0, 0.0};
+    const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
+    double vi[3] = {0.0, 0.0, 0.0};
+    if (!a.newton_only) {
+      vi[0] = a.vel[3 * i];
+      vi[1] = a.vel[3 * i + 1];
+      vi[2] = a.vel[3 * i + 2];
+      const double vi2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
+      double Vphi = Vi;
+      double aNs[3] = {aN[0], aN[1], aN[2]};
+      if (a.phi_in) {  // correction mode: the caller's potential and Newtonian acceleration
+        Vphi = -a.phi_in[i];
+        aNs[0] = a.accN_in[3 * i];
+        aNs[1] = a.accN_in[3 * i + 1];
+        aNs[2] = a.accN_in[3 * i + 2];
+      }
+      // Eq. (6) star-star terms: S_i0 G_i + Q_i + C2_i v_i + 7 Q7_i, S_i0 = -v_i^2 + 4 u_i
+      const double Si0 = -vi2 + 4.0 * ui;
+      double q[3];
+      for (int c = 0; c < 3; ++c)
+        q[c] = Si0 * sum[F_G + c] + sum[F_Q + c] + sum[F_C2] * vi[c] + 7.0 * sum[F_Q7 + c];
+      // massive-object partner (Eq. (5) and the G^2 m M / velocity terms of Eq. (6))
+      const double d0[3] = {xi - x0, yi - y0, zi - z0};
+      const double rinv0 = rsqrt_f64(d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2] + a.eps2);
+      const double n0[3] = {d0[0] * rinv0, d0[1] * rinv0, d0[2] * rinv0};
+      const double kk = gM * rinv0 * rinv0;
+      const double vw = vi[0] * w[0] + vi[1] * w[1] + vi[2] * w[2];
+      const double dA = d0[0] * A0[0] + d0[1] * A0[1] + d0[2] * A0[2];
+      const double br = -vi2 + 4.0 * vw + 4.0 * Vphi + V0 + 0.5 * dA;
+      const double n4v = 4.0 * (n0[0] * vi[0] + n0[1] * vi[1] + n0[2] * vi[2]);
+      const double nw = n0[0] * w[0] + n0[1] * w[1] + n0[2] * w[2];
+      const double g7 = 3.5 * gM * rinv0;
+      for (int c = 0; c < 3; ++c) {
+        const double B = kk * (br * n0[c] + n4v * (vi[c] - w[c]) - 3.0 * nw * vi[c]) + g7 * A0[c];
+        a1[c] = a.lam * (B + q[c]);
+      }
+      // this star's term of the massive object's 1PN sum (Eqs. (2)-(3))
+      const double Vs = Vphi;
+      const double gm_s = a.G * a.mass[i];
+      const double ks = gm_s * rinv0 * rinv0;
+      const double n0s[3] = {-n0[0], -n0[1], -n0[2]};
+      const double d0s[3] = {-d0[0], -d0[1], -d0[2]};
+      const double nvs = n0s[0] * vi[0] + n0s[1] * vi[1] + n0s[2] * vi[2];
+      const double dAs = d0s[0] * aNs[0] + d0s[1] * aNs[1] + d0s[2] * aNs[2];
+      const double brs = -2.0 * vi2 + 4.0 * vw + 1.5 * nvs * nvs + 4.0 * V0 + Vs + 0.5 * dAs;
+      const double nws = n0s[0] * w[0] + n0s[1] * w[1] + n0s[2] * w[2];
+      const double g7s = 3.5 * gm_s * rinv0;
+      for (int c = 0; c < 3; ++c)
+        bh[c] = ks * (brs * n0s[c] + 3.0 * nvs * vi[c] - 3.0 * nvs * w[c] - 4.0 * nws * vi[c]) +
+                g7s * aNs[c];
+    }
+    if (a.acc_newton) {
+      a.acc_newton[3 * i] = aN[0];
+      a.acc_newton[3 * i + 1] = aN[1];
+      a.acc_newton[3 * i + 2] = aN[2];
+    }
+    if (a.phi) a.phi[i] = -Vi;
+    if (a.acc_1pn) {
+      a.acc_1pn[3 * i] = a1[0];
+      a.acc_1pn[3 * i + 1] = a1[1];
+      a.acc_1pn[3 * i + 2] = a1[2];
+    }
+    const double at[3] = {aN[0] + a1[0], aN[1] + a1[1], aN[2] + a1[2]};
+    if (!isfinite(at[0]) || !isfinite(at[1]) || !isfinite(at[2])) atomicOr(a.status, 1);
+    if (a.stage >= 0) {
+      for (int c = 0; c < 3; ++c) rk4_update(a, 3 * (size_t)i + c, vi[c], at[c]);
+    }
+  }
+  double bhs[3] = {bh[0], bh[1], bh[2]};
+  block_sum<3>(bhs, lds);
+  if (threadIdx.x < 4)
+    a.bhpart[(size_t)blockIdx.x * 4 + threadIdx.x] = threadIdx.x < 3 ? lds[threadIdx.x * kBlock] : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bh_final(EpiArgs a) {
+  __shared__ double lds[7 * kBlock];
+  double A0[3], V0, P[3];
+  bh_quantities(a, lds, A0, V0, P);
+  double T[3] = {0.0, 0.0, 0.0};
+  if (!a.newton_only) reduce_rows<3>(a.bhpart, a.nbepi, 4, lds, T);
+  if (threadIdx.x == 0) {
+    double a1[3], at[3], v0[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < 3; ++c) {
+      a1[c] = a.lam * T[c];
+      at[c] = A0[c] + a1[c];
+    }
+    if (!a.newton_only) {
+      v0[0] = a.vel[0];
+      v0[1] = a.vel[1];
+      v0[2] = a.vel[2];
+    }
+    if (a.acc_newton) {
+      a.acc_newton[0] = A0[0];
+      a.acc_newton[1] = A0[1];
+      a.acc_newton[2] = A0[2];
+    }
+    if (a.phi) a.phi[0] = -V0;
+    if (a.acc_1pn) {
+      a.acc_1pn[0] = a1[0];
+      a.acc_1pn[1] = a1[1];
+      a.acc_1pn[2] = a1[2];
+    }
+    if (!isfinite(at[0]) || !isfinite(at[1]) || !isfinite(at[2])) atomicOr(a.status, 1);
+    if (a.stage >= 0) {
+      for (int c = 0; c < 3; ++c) rk4_update(a, (size_t)c, v0[c], at[c]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics (Eqs. (7)-(8)).  Star-star pair sums per star i:
+//   U_i = sum_j G m_j / R_ij
+//   W_i = sum_j (G m_j / R_ij) [-7 v_i.v_j - (n_ij.v_i)(n_ij.v_j)]
+//   Y_i = sum_j (G m_j / R_ij) (v_i.n_ij) n_ij
+// then O(N) terms per star and fixed-order reductions.
+// ---------------------------------------------------------------------------
+constexpr int kND = 5;  // U, W, Y(3)
+
+struct DiagPairArgs {
+  const PkF64* pk;
+  int Ns, jchunk;
+  double eps2;
+  double* part;  // [gridDim.y][kND][Ns]
+};
+
+__global__ __launch_bounds__(kBlock) void k_diag_pair(DiagPairArgs a) {
+  const PkF64* __restrict__ pk = a.pk;
+  const int ilo = blockIdx.x * kBlock;
+  const int ihi = min(a.Ns, ilo + kBlock);
+  const int i = ilo + threadIdx.x;
+  const PkF64& pi = pk[min(i, a.Ns - 1)];
+  const double xi = pi.x, yi = pi.y, zi = pi.z, vxi = pi.vx, vyi = pi.vy, vzi = pi.vz;
+  const int j0 = blockIdx.y * a.jchunk, j1 = min(a.Ns, j0 + a.jchunk);
+  double U = 0.0, W = 0.0, Yx = 0.0, Yy = 0.0, Yz = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const PkF64& p = pk[j];
+    const double dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
+    double rinv = rsqrt_f64(fma(dz, dz, fma(dy, dy, fma(dx, dx, a.eps2))));
+    if (j >= ilo && j < ihi) rinv = (j == i) ? 0.0 : rinv;
+    const double mr = p.gm * rinv;
+    const double rinv2 = rinv * rinv;
+    const double vv = fma(vzi, p.vz, fma(vyi, p.vy, vxi * p.vx));
+    const double xvi = fma(dz, vzi, fma(dy, vyi, dx * vxi));
+    const double xvj = fma(dz, p.vz, fma(dy, p.vy, dx * p.vx));
+    U += mr;
+    W = fma(mr, fma(-xvi * xvj, rinv2, -7.0 * vv), W);
+    const double cy = mr * xvi * rinv2;
+    Yx = fma(cy, dx, Yx);
+    Yy = fma(cy, dy, Yy);
+    Yz = fma(cy, dz, Yz);
+  }
+  if (i < a.Ns) {
+    const size_t plane = (size_t)a.Ns;
+    double* out = a.part + (size_t)blockIdx.y * kND * plane + i;
+    out[0] = U;
+    out[plane] = W;
+    out[2 * plane] = Yx;
+    out[3 * plane] = Yy;
+    out[4 * plane] = Yz;
+  }
+}
+
+struct DiagEpiArgs {
+  const double* pos;
+  const double* vel;
+  const double* mass;
+  int Ns;
+  double G, lam, eps2;
+  const double* ub;
+  const double* part;
+  int nsplit;
+  double* dpart;  // [gridDim.x][10]
+  int ndpart;     // (k_diag_final) rows of dpart
+  double* out8;   // (k_diag_final)
+};
+
+// Per-star contributions, columns of dpart:
+//  0: 1/2 m v^2 - 1/2 m U - m u          (Newtonian energy, stars)
+//  1: 1PN energy bracket, star terms
+//  2: m u / M  (sum = U0 = sum_i G m_i / R_1i)
+//  3-5: m v                               (Newtonian momentum, stars)
+//  6-8: 1PN momentum bracket, star terms
+__global__ __launch_bounds__(kBlock) void k_diag_epi(DiagEpiArgs a) {
+  __shared__ double lds[9 * kBlock];
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (k < a.Ns) {
+    const int i = k + 1;
+    const size_t plane = (size_t)a.Ns;
+    double U = 0.0, W = 0.0, Y[3] = {0.0, 0.0, 0.0};
+    for (int sp = 0; sp < a.nsplit; ++sp) {
+      const double* pp = a.part + (size_t)sp * kND * plane + k;
+      U += pp[0];
+      W += pp[plane];
+      Y[0] += pp[2 * plane];
+      Y[1] += pp[3 * plane];
+      Y[2] += pp[4 * plane];
+    }
+    const double M = a.mass[0], m = a.mass[i];
+    const double u = a.ub[4 * (size_t)k];
+    const double* vi = a.vel + 3 * i;
+    const double* v1 = a.vel;
+    const double d[3] = {a.pos[0] - a.pos[3 * i], a.pos[1] - a.pos[3 * i + 1],
+                         a.pos[2] - a.pos[3 * i + 2]};  // x_1i
+    const double rinv = rsqrt_f64(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + a.eps2);
+    const double n[3] = {d[0] * rinv, d[1] * rinv, d[2] * rinv};
+    const double vi2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
+    const double v12 = v1[0] * v1[0] + v1[1] * v1[1] + v1[2] * v1[2];
+    const double v1vi = v1[0] * vi[0] + v1[1] * vi[1] + v1[2] * vi[2];
+    const double nv1 = n[0] * v1[0] + n[1] * v1[1] + n[2] * v1[2];
+    const double nvi = n[0] * vi[0] + n[1] * vi[1] + n[2] * vi[2];
+    v[0] = 0.5 * m * vi2 - 0.5 * m * U - m * u;
+    v[1] = 0.375 * m * vi2 * vi2 + 1.5 * m * u * vi2 + 0.5 * m * u * u +
+           0.25 * m * (6.0 * vi2 * U + W) + 0.5 * m * u * (3.0 * v12 - 7.0 * v1vi - nv1 * nvi) +
+           m * u * U;
+    v[2] = m * u / M;
+    for (int c = 0; c < 3; ++c) {
+      v[3 + c] = m * vi[c];
+      v[6 + c] = 0.5 * m * vi2 * vi[c] - 0.5 * m * u * (vi[c] + nvi * n[c]) -
+                 0.5 * m * u * (v1[c] + nv1 * n[c]) - 0.5 * m * (U * vi[c] + Y[c]);
+    }
+  }
+  block_sum<9>(v, lds);
+  if (threadIdx.x < 10)
+    a.dpart[(size_t)blockIdx.x * 10 + threadIdx.x] = threadIdx.x < 9 ? lds[threadIdx.x * kBlock] : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_diag_final(DiagEpiArgs a) {
+  __shared__ double lds[9 * kBlock];
+  double r[9];
+  reduce_rows<9>(a.dpart, a.ndpart, 10, lds, r);
+  if (threadIdx.x == 0) {
+    const double M = a.mass[0];
+    const double* v1 = a.vel;
+    const double v12 = v1[0] * v1[0] + v1[1] * v1[1] + v1[2] * v1[2];
+    const double U0 = r[2];
+    a.out8[0] = 0.5 * M * v12 + r[0];
+    a.out8[1] = a.lam * (r[1] + 0.5 * M * U0 * U0);
+    for (int c = 0; c < 3; ++c) {
+      a.out8[2 + c] = M * v1[c] + r[3 + c];
+      a.out8[5 + c] = a.lam * r[6 + c];
+    }
+  }
+}
+
+}  // namespace pn

@@ -1,0 +1,121 @@
+"""The C ABI library: loads on a machine without a GPU, exports every entry
+point include/pn.h declares, and rejects invalid arguments before any device
+work (so these run on the CPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pn.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(pn_\w+)\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1801_07986_amd import _binding
+
+    if not os.path.exists(_binding.LIB_PATH):
+        from paper_1801_07986_amd import build
+
+        build.build()
+    return _binding.load()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for required in ("pn_potential_accel", "pn_correction", "pn_step", "pn_accel",
+                     "pn_diagnostics", "pn_step_batched", "pn_strerror", "pn_release",
+                     "pn_last_timing"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1801_07986_amd import _binding
+
+    out = subprocess.run(["nm", "-D", "--defined-only", _binding.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (pn_\w+)$", out, re.M))
+    for name in _declared():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_library_holds_gfx950_code(lib):
+    from paper_1801_07986_amd import _binding
+
+    blob = open(_binding.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob
+
+
+FAKE = ctypes.c_void_p(4096)  # aligned, never dereferenced: validation fails first
+MIS = ctypes.c_void_p(4097)   # misaligned
+
+
+def test_validation_without_device(lib):
+    EINVAL = -1
+    d = FAKE
+    # N < 2
+    assert lib.pn_potential_accel(d, d, d, 1, 1.0, 30.0, 0.0, d, d, None, 0) == EINVAL
+    # G <= 0, c <= 0, c NaN, eps < 0, eps inf
+    assert lib.pn_potential_accel(d, d, d, 16, 0.0, 30.0, 0.0, d, d, None, 0) == EINVAL
+    assert lib.pn_potential_accel(d, d, d, 16, 1.0, -1.0, 0.0, d, d, None, 0) == EINVAL
+    assert lib.pn_potential_accel(d, d, d, 16, 1.0, float("nan"), 0.0, d, d, None, 0) == EINVAL
+    assert lib.pn_potential_accel(d, d, d, 16, 1.0, 30.0, -1e-3, d, d, None, 0) == EINVAL
+    assert lib.pn_potential_accel(d, d, d, 16, 1.0, 30.0, float("inf"), d, d, None, 0) == EINVAL
+    # null or misaligned pointers
+    assert lib.pn_potential_accel(None, d, d, 16, 1.0, 30.0, 0.0, d, d, None, 0) == EINVAL
+    assert lib.pn_potential_accel(MIS, d, d, 16, 1.0, 30.0, 0.0, d, d, None, 0) == EINVAL
+    assert lib.pn_correction(d, None, d, 16, 1.0, 30.0, 0.0, d, d, d, None, 0) == EINVAL
+    assert lib.pn_correction(d, d, d, 16, 1.0, 30.0, 0.0, None, d, d, None, 0) == EINVAL
+    # pn_step: bad dt, negative nsteps, unknown precision
+    assert lib.pn_step(d, d, d, 16, 1.0, 30.0, 0.0, float("nan"), 1, 0, None, 0) == EINVAL
+    assert lib.pn_step(d, d, d, 16, 1.0, 30.0, 0.0, 1e-4, -1, 0, None, 0) == EINVAL
+    assert lib.pn_step(d, d, d, 16, 1.0, 30.0, 0.0, 1e-4, 1, 7, None, 0) == EINVAL
+    assert lib.pn_accel(d, d, d, 16, 1.0, 30.0, 0.0, 9, d, d, d, None, 0) == EINVAL
+    assert lib.pn_diagnostics(d, d, d, 16, 1.0, 30.0, 0.0, None, None, 0) == EINVAL
+    assert lib.pn_last_timing(None) == EINVAL
+
+
+def test_batched_validation_without_device(lib):
+    EINVAL = -1
+    d = FAKE
+    off = (ctypes.c_int64 * 3)(0, 10, 11)  # second system has a single body
+    p = (ctypes.c_double * 2)(1.0, 1.0)
+    cast = lambda a: ctypes.cast(a, ctypes.c_void_p)  # noqa: E731
+    assert lib.pn_step_batched(2, cast(off), cast(p), cast(p), cast(p), d, d, d, 1e-4, 1, 0,
+                               None, 0) == EINVAL
+    off = (ctypes.c_int64 * 3)(1, 10, 20)  # must start at 0
+    assert lib.pn_step_batched(2, cast(off), cast(p), cast(p), cast(p), d, d, d, 1e-4, 1, 0,
+                               None, 0) == EINVAL
+    assert lib.pn_step_batched(0, cast(off), cast(p), cast(p), cast(p), d, d, d, 1e-4, 1, 0,
+                               None, 0) == EINVAL
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, 99):
+        assert isinstance(lib.pn_strerror(code), bytes)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1801_07986_amd import _binding
+
+    monkeypatch.setattr(_binding, "_lib", None)
+    monkeypatch.setattr(_binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _binding.load()
+
+
+def test_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    from paper_1801_07986_amd import _binding
+
+    x = torch.zeros(4, 3, dtype=torch.float64)
+    with pytest.raises(TypeError):
+        _binding._ptr(x)

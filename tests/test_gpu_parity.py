@@ -1,0 +1,299 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (relative, per body, Euclidean norm of the 3-vector):
+  FP64 path:  total acceleration <= 1e-12, 1PN part <= 1e-10, potential <= 1e-12
+  mixed path: total acceleration <= 1e-6,  1PN part <= 1e-4
+The FP64 bound is the accuracy target of the method's FP64 path; the 1PN part
+is reported separately because at c = 30-50 it is only ~1e-4 of the total.
+
+Per-body error: |a - a_ref| / max(|a_ref|, s / 1000), where s = sum_b G m_b /
+R_ib^2 is the summed magnitude of the body's Newtonian pair terms.  This is
+the plain relative error unless the terms cancel by more than a factor 1000
+(a body at a symmetry point, e.g. the massive object between two stars placed
+opposite each other, has a_ref = 0 and only rounding is left on either side).
+For the 1PN part the floor is 1e-6 s.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_07986_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+G = 1.0
+TOL_FP64, TOL_FP64_1PN = 1e-12, 1e-10
+TOL_MIXED, TOL_MIXED_1PN = 1e-6, 1e-4
+
+
+@pytest.fixture(scope="module")
+def pn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_07986_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def newton_scale(pos, mass, eps, rows=None, chunk=256):
+    """s_i = sum_{b != i} G m_b / (r_ib^2 + eps^2) for the given rows."""
+    rows = np.arange(len(mass)) if rows is None else np.asarray(rows)
+    out = np.empty(len(rows))
+    for k in range(0, len(rows), chunk):
+        r = rows[k:k + chunk]
+        d = pos[r][:, None, :] - pos[None, :, :]
+        R2 = (d * d).sum(-1) + eps * eps
+        t = G * mass[None, :] / np.where(R2 > 0, R2, np.inf)
+        t[np.arange(len(r)), r] = 0.0
+        out[k:k + chunk] = t.sum(1)
+    return out
+
+
+def body_rel(a, b, scale, floor=1e-3):
+    num = np.linalg.norm(a - b, axis=-1)
+    den = np.maximum(np.linalg.norm(b, axis=-1), floor * scale)
+    return num / den
+
+
+def gpu_accel(pn, pos, vel, mass, c, eps, precision):
+    N = len(mass)
+    aN = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    phi = torch.empty(N, dtype=torch.float64, device="cuda:0")
+    a1 = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    pn.pn_accel(dev(pos), dev(vel), dev(mass), G, c, eps, precision, aN, phi, a1)
+    return host(aN), host(phi), host(a1)
+
+
+def case(N, seed, M=0.1):
+    print(f"[case] N={N} seed={seed} M={M}", flush=True)
+    return inputs.plummer_bh(N, M, seed)
+
+
+SIZES = [2, 3, 17, 64, 257, 1000, 1024, 2049]
+
+
+@pytest.mark.parametrize("N", SIZES)
+def test_potential_accel_fp64(pn, N):
+    pos, vel, mass = case(N, 100 + N)
+    eps = 1e-4
+    aN = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    phi = torch.empty(N, dtype=torch.float64, device="cuda:0")
+    pn.pn_potential_accel(dev(pos), None, dev(mass), G, 50.0, eps, aN, phi)
+    rN, rphi = oracle.newton(pos, mass, G, eps)
+    assert body_rel(host(aN), rN, newton_scale(pos, mass, eps)).max() <= TOL_FP64
+    assert (np.abs(host(phi) - rphi) / np.abs(rphi)).max() <= TOL_FP64
+
+
+@pytest.mark.parametrize("N", SIZES)
+def test_correction_fp64(pn, N):
+    pos, vel, mass = case(N, 200 + N)
+    c, eps = 30.0, 1e-4
+    rN, rphi, r1 = oracle.accel(pos, vel, mass, G, c, eps)
+    out = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    pn.pn_correction(dev(pos), dev(vel), dev(mass), G, c, eps, dev(rphi), dev(rN), out)
+    s = newton_scale(pos, mass, eps)
+    assert body_rel(host(out), r1, s, 1e-6).max() <= TOL_FP64_1PN
+    assert body_rel(rN + host(out), rN + r1, s).max() <= TOL_FP64
+
+
+def test_potential_then_correction_chain(pn):
+    """pn_correction on pn_potential_accel's own outputs, as a caller would chain them."""
+    N = 1500
+    pos, vel, mass = case(N, 7)
+    c, eps = 50.0, 1e-4
+    P, V, Mm = dev(pos), dev(vel), dev(mass)
+    aN = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    phi = torch.empty(N, dtype=torch.float64, device="cuda:0")
+    a1 = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    pn.pn_potential_accel(P, V, Mm, G, c, eps, aN, phi)
+    pn.pn_correction(P, V, Mm, G, c, eps, phi, aN, a1)
+    rN, rphi, r1 = oracle.accel(pos, vel, mass, G, c, eps)
+    s = newton_scale(pos, mass, eps)
+    assert body_rel(host(aN) + host(a1), rN + r1, s).max() <= TOL_FP64
+    assert body_rel(host(a1), r1, s, 1e-6).max() <= TOL_FP64_1PN
+
+
+@pytest.mark.parametrize("N", SIZES)
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_accel(pn, N, precision):
+    pos, vel, mass = case(N, 300 + N)
+    c, eps = 30.0, 1e-4
+    aN, phi, a1 = gpu_accel(pn, pos, vel, mass, c, eps, precision)
+    rN, rphi, r1 = oracle.accel(pos, vel, mass, G, c, eps)
+    tol, tol1 = (TOL_FP64, TOL_FP64_1PN) if precision == 0 else (TOL_MIXED, TOL_MIXED_1PN)
+    s = newton_scale(pos, mass, eps)
+    e_tot = body_rel(aN + a1, rN + r1, s)
+    e_1pn = body_rel(a1, r1, s, 1e-6)
+    print(f"N={N} prec={precision} max rel total {e_tot.max():.3e} 1PN {e_1pn.max():.3e}")
+    assert e_tot.max() <= tol
+    assert e_1pn.max() <= tol1
+    assert (np.abs(phi - rphi) / np.abs(rphi)).max() <= (TOL_FP64 if precision == 0 else TOL_MIXED)
+
+
+def test_no_softening(pn):
+    pos, vel, mass = case(300, 11)
+    aN, phi, a1 = gpu_accel(pn, pos, vel, mass, 20.0, 0.0, 0)
+    rN, rphi, r1 = oracle.accel(pos, vel, mass, G, 20.0, 0.0)
+    assert body_rel(aN + a1, rN + r1, newton_scale(pos, mass, 0.0)).max() <= TOL_FP64
+
+
+def test_newtonian_limit_exact(pn):
+    pos, vel, mass = case(500, 12)
+    aN, phi, a1 = gpu_accel(pn, pos, vel, mass, math.inf, 1e-4, 0)
+    assert np.all(a1 == 0.0)
+    rN, _ = oracle.newton(pos, mass, G, 1e-4)
+    assert body_rel(aN, rN, newton_scale(pos, mass, 1e-4)).max() <= TOL_FP64
+
+
+def test_deterministic(pn):
+    pos, vel, mass = case(3000, 13)
+    for prec in (0, 1):
+        a = gpu_accel(pn, pos, vel, mass, 30.0, 1e-4, prec)
+        b = gpu_accel(pn, pos, vel, mass, 30.0, 1e-4, prec)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_invalid_mass_detected_on_device(pn):
+    pos, vel, mass = case(64, 14)
+    mass[0] = 0.0
+    with pytest.raises(pn.PNError) as e:
+        gpu_accel(pn, pos, vel, mass, 30.0, 1e-4, 0)
+    assert e.value.code == pn.PN_EINVAL
+
+
+def test_nonfinite_reported(pn):
+    pos, vel, mass = case(64, 15)
+    pos[5] = pos[9]  # two coincident stars without softening
+    with pytest.raises(pn.PNError) as e:
+        gpu_accel(pn, pos, vel, mass, 30.0, 0.0, 0)
+    assert e.value.code == pn.PN_ENONFINITE
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_step_trajectory_n1024(pn, precision):
+    """Plummer N = 1024 (M = 0.1, c = 50, eps = 1e-4): 100 RK4 steps of 1e-4
+    against the oracle's trajectory."""
+    w = inputs.WORKLOADS["plummer_n1024_fp64"]
+    pos, vel, mass = inputs.plummer_bh(w["N"], w["M_bh"], w["seed"])
+    P, V = dev(pos), dev(vel)
+    pn.pn_step(P, V, dev(mass), G, w["c"], w["eps"], w["dt"], w["steps"], precision)
+    rp, rv = oracle.step(pos, vel, mass, G, w["c"], w["eps"], w["dt"], w["steps"])
+    dp = np.abs(host(P) - rp).max() / np.abs(rp).max()
+    dv = (np.linalg.norm(host(V) - rv, axis=1) / np.linalg.norm(rv, axis=1).max()).max()
+    print(f"prec={precision} trajectory: max |dx|/max|x| {dp:.3e}, max per-body |dv|/max|v| {dv:.3e}")
+    if precision == 0:
+        assert dp <= 1e-12 and dv <= 1e-10
+    else:
+        assert dp <= 1e-8 and dv <= 1e-6
+
+
+def test_step_graph_equals_direct_launches(pn):
+    pos, vel, mass = case(777, 16)
+    outs = []
+    for flags in (0, pn.PN_NOGRAPH):
+        P, V = dev(pos), dev(vel)
+        pn.pn_step(P, V, dev(mass), G, 40.0, 1e-4, 1e-4, 5, 0, flags=flags)
+        outs.append((host(P), host(V)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_step_zero_is_noop(pn):
+    pos, vel, mass = case(100, 17)
+    P, V = dev(pos), dev(vel)
+    pn.pn_step(P, V, dev(mass), G, 40.0, 1e-4, 1e-4, 0, 0)
+    assert np.array_equal(host(P), pos) and np.array_equal(host(V), vel)
+
+
+def test_step_resume_is_bitwise(pn):
+    """k steps then m steps equals k+m steps (checkpoint/resume of the state)."""
+    pos, vel, mass = case(600, 18)
+    P1, V1 = dev(pos), dev(vel)
+    pn.pn_step(P1, V1, dev(mass), G, 40.0, 1e-4, 1e-4, 7, 0)
+    P2, V2 = dev(pos), dev(vel)
+    pn.pn_step(P2, V2, dev(mass), G, 40.0, 1e-4, 1e-4, 3, 0)
+    P2h, V2h = host(P2).copy(), host(V2).copy()  # "checkpoint"
+    P3, V3 = dev(P2h), dev(V2h)
+    pn.pn_step(P3, V3, dev(mass), G, 40.0, 1e-4, 1e-4, 4, 0)
+    assert np.array_equal(host(P1), host(P3)) and np.array_equal(host(V1), host(V3))
+
+
+@pytest.mark.parametrize("N", [2, 64, 1024, 2049])
+def test_diagnostics(pn, N):
+    pos, vel, mass = case(N, 400 + N)
+    vel[0] = [0.01, -0.02, 0.005]
+    c, eps = 30.0, 1e-4
+    got = np.array(pn.pn_diagnostics(dev(pos), dev(vel), dev(mass), G, c, eps))
+    ref = oracle.diagnostics(pos, vel, mass, G, c, eps)
+    assert abs(got[0] - ref[0]) <= 1e-12 * abs(ref[0])
+    assert abs(got[1] - ref[1]) <= 1e-12 * abs(ref[1])
+    scaleP = np.abs(mass[:, None] * vel).sum()
+    assert np.abs(got[2:5] - ref[2:5]).max() <= 1e-13 * scaleP
+    assert np.abs(got[5:8] - ref[5:8]).max() <= 1e-12 * np.abs(ref[5:8]).max()
+
+
+# ---------------------------------------------------------------- full sizes
+def _sample_rows(pos, n_near, n_rand, seed):
+    N = len(pos)
+    r = np.linalg.norm(pos[1:] - pos[0], axis=1)
+    near = 1 + np.argsort(r)[:n_near]
+    rng = np.random.default_rng(seed)
+    rest = np.setdiff1d(np.arange(1, N), near)
+    rand = rng.choice(rest, size=min(n_rand, len(rest)), replace=False)
+    return np.concatenate([[0], near, np.sort(rand)]).astype(np.int64)
+
+
+def test_full_size_n16384_fp64(pn):
+    """N = 16384 Plummer (M = 0.05, c = 30, eps = 1e-4), FP64, the launch shape
+    the benchmark uses: the massive object, the 63 stars nearest to it and 448
+    random stars against the oracle row by row."""
+    w = inputs.WORKLOADS["plummer_n16384_fp64"]
+    pos, vel, mass = inputs.plummer_bh(w["N"], w["M_bh"], w["seed"])
+    aN, phi, a1 = gpu_accel(pn, pos, vel, mass, w["c"], w["eps"], 0)
+    rows = _sample_rows(pos, 63, 448, 1)
+    rN, rphi, r1 = oracle.accel_rows(pos, vel, mass, G, w["c"], w["eps"], rows)
+    s = newton_scale(pos, mass, w["eps"], rows)
+    e = body_rel(aN[rows] + a1[rows], rN + r1, s)
+    e1 = body_rel(a1[rows], r1, s, 1e-6)
+    print(f"N=16384 fp64: max rel total {e.max():.3e}, 1PN {e1.max():.3e}")
+    assert e.max() <= TOL_FP64 and e1.max() <= TOL_FP64_1PN
+
+
+def test_full_size_n16384_one_step(pn):
+    """One RK4 step of the N = 16384 workload against the oracle's step."""
+    w = inputs.WORKLOADS["plummer_n16384_fp64"]
+    pos, vel, mass = inputs.plummer_bh(w["N"], w["M_bh"], w["seed"])
+    P, V = dev(pos), dev(vel)
+    pn.pn_step(P, V, dev(mass), G, w["c"], w["eps"], w["dt"], 1, 0)
+    rp, rv = oracle.step(pos, vel, mass, G, w["c"], w["eps"], w["dt"], 1)
+    assert np.abs(host(P) - rp).max() <= 1e-14 * np.abs(rp).max()
+    assert np.abs(host(V) - rv).max() <= 1e-12 * np.abs(rv).max()
+
+
+def test_full_size_n65536_mixed(pn):
+    """N = 65536 Plummer (M = 0.1, c = 30, eps = 1e-4), mixed precision: the
+    massive object, the 63 stars nearest to it and 4032 random stars."""
+    w = inputs.WORKLOADS["plummer_n65536_mixed"]
+    pos, vel, mass = inputs.plummer_bh(w["N"], w["M_bh"], w["seed"])
+    aN, phi, a1 = gpu_accel(pn, pos, vel, mass, w["c"], w["eps"], 1)
+    rows = _sample_rows(pos, 63, 4032, 2)
+    rN, rphi, r1 = oracle.accel_rows(pos, vel, mass, G, w["c"], w["eps"], rows)
+    s = newton_scale(pos, mass, w["eps"], rows)
+    e = body_rel(aN[rows] + a1[rows], rN + r1, s)
+    e1 = body_rel(a1[rows], r1, s, 1e-6)
+    print(f"N=65536 mixed: max rel total {e.max():.3e} median {np.median(e):.3e}, "
+          f"1PN max {e1.max():.3e}")
+    assert e.max() <= TOL_MIXED and e1.max() <= TOL_MIXED_1PN
