@@ -136,6 +136,16 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
                     const double* eps, double* pos, double* vel, const double* mass, double dt,
                     int64_t nsteps, int precision, void* stream, int flags);
 
+/*
+ * Launch shape of the star-star sweep for systems with n_min <= N <= n_max in
+ * the given precision (searched by the autotuner; later entries never override
+ * earlier ones that match).  ipt: i-bodies per lane (1 or 2); ws: wavefronts
+ * sharing one i-range (1 or 4); nsplit: j-range splits (0 = default rule).
+ * precision < 0 clears the table.  Shapes change speed only: results of a
+ * given shape are deterministic and every shape meets the same accuracy.
+ */
+int pn_set_shape(int precision, int64_t n_min, int64_t n_max, int ipt, int ws, int nsplit);
+
 /* Text for a return code (PN_EDEVICE: the last HIP error seen).  Never NULL. */
 const char* pn_strerror(int code);
 

@@ -19,7 +19,8 @@ PN_FP64, PN_MIXED = 0, 1
 PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
 
 EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
-           "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release")
+           "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape")
+TUNED_PATH = os.path.join(HERE, "tuned_shapes.json")
 
 
 class PNError(RuntimeError):
@@ -51,11 +52,36 @@ def load():
         lib.pn_strerror.restype = ctypes.c_char_p
         lib.pn_last_timing.argtypes = [vp]
         lib.pn_release.argtypes = []
+        lib.pn_set_shape.argtypes = [i32, i64, i64, i32, i32, i32]
         for name in EXPORTS:
             if name != "pn_strerror":
                 getattr(lib, name).restype = i32
         _lib = lib
+        install_tuned_shapes()
     return _lib
+
+
+def install_tuned_shapes(path: str | None = None) -> int:
+    """Install the autotuner's shape table (tuned_shapes.json) into the library."""
+    import json
+
+    path = path or TUNED_PATH
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        table = json.load(f)
+    _lib.pn_set_shape(-1, 0, 0, 0, 0, 0)
+    n = 0
+    for e in table.get("entries", []):
+        prec = PN_MIXED if e["precision"] == "mixed" else PN_FP64
+        _check(_lib.pn_set_shape(prec, int(e["n_min"]), int(e["n_max"]), int(e["ipt"]),
+                                 int(e["ws"]), int(e["nsplit"])), "pn_set_shape")
+        n += 1
+    return n
+
+
+def pn_set_shape(precision, n_min, n_max, ipt, ws, nsplit):
+    return _check(load().pn_set_shape(precision, n_min, n_max, ipt, ws, nsplit), "pn_set_shape")
 
 
 def _check(rc: int, name: str) -> int:

@@ -35,32 +35,53 @@ int fail_hip(hipError_t e, const char* what, int line) {
 
 // ------------------------------------------------------------------ launch shapes
 struct Shape {
-  int ipt = 1;     // i-bodies per thread
+  int ipt = 1;     // i-bodies per lane
+  int ws = 4;      // wavefronts sharing one i-range (1 or 4)
   int nsplit = 1;  // j splits (gridDim.y)
   int jchunk = 1;  // j per split
   int iblocks = 1; // gridDim.x
 };
 
-// Default shape: enough workgroups to give every SIMD of the 256 compute
-// units several wavefronts, splitting the j range when the i range alone is
-// too short.  PN_SHAPE="ipt,nsplit" overrides (used by the tuner).
+// Tuned shapes installed with pn_set_shape (searched by the autotuner).
+struct TunedShape {
+  int precision;
+  int64_t n_min, n_max;
+  int ipt, ws, nsplit;
+};
+std::vector<TunedShape> g_tuned;
+
+// Shape: a tuned entry if one covers (precision, N), else the default: four
+// wavefronts per i-range, one i per lane, and 16 j-splits (measured best for
+// the whole evaluation at N = 16k-64k on MI355X: enough workgroups in flight
+// without making the epilogue's split reduction dominate), at least 32 j per
+// wavefront.  PN_SHAPE="ipt,ws,nsplit" overrides everything (tuning runs).
 Shape pick_shape(int Ns, int precision) {
   Shape s;
   s.ipt = 1;
-  (void)precision;
+  s.ws = 4;
   int want_nsplit = 0;
-  if (const char* env = getenv("PN_SHAPE")) {
-    int a = 0, b = 0;
-    if (sscanf(env, "%d,%d", &a, &b) == 2 && (a == 1 || a == 2) && b >= 1) {
-      s.ipt = a;
-      want_nsplit = b;
+  for (const TunedShape& t : g_tuned) {
+    if (t.precision == precision && Ns + 1 >= t.n_min && Ns + 1 <= t.n_max) {
+      s.ipt = t.ipt;
+      s.ws = t.ws;
+      want_nsplit = t.nsplit;
+      break;
     }
   }
-  s.iblocks = (Ns + kBlock * s.ipt - 1) / (kBlock * s.ipt);
+  if (const char* env = getenv("PN_SHAPE")) {
+    int a = 0, b = 0, c = 0;
+    if (sscanf(env, "%d,%d,%d", &a, &b, &c) == 3 && (a == 1 || a == 2) && (b == 1 || b == 4) &&
+        c >= 0) {
+      s.ipt = a;
+      s.ws = b;
+      want_nsplit = c;
+    }
+  }
+  const int ib = kBlock / s.ws * s.ipt;  // i-bodies per workgroup
+  s.iblocks = (Ns + ib - 1) / ib;
   if (want_nsplit <= 0) {
-    const int target = 2048;  // workgroups: 256 CUs x 8
-    want_nsplit = (target + s.iblocks - 1) / s.iblocks;
-    want_nsplit = std::min(want_nsplit, std::max(1, Ns / 128));
+    want_nsplit = std::max(16, (4096 + s.iblocks - 1) / s.iblocks);
+    want_nsplit = std::min(want_nsplit, std::max(1, Ns / (32 * s.ws)));
   }
   want_nsplit = std::max(1, std::min(want_nsplit, Ns));
   s.jchunk = (Ns + want_nsplit - 1) / want_nsplit;
@@ -89,7 +110,7 @@ Layout layout_for(int64_t N, const Shape& s, bool rk4) {
   L.ub = take(Ns * 4 * sizeof(double));
   L.bpart = take(nb * 8 * sizeof(double));
   L.part = take((size_t)s.nsplit * std::max(kNF, kND) * Ns * sizeof(double));
-  L.bhpart = take(nb * 4 * sizeof(double));
+  L.bhpart = take(((Ns + kEpiStars - 1) / kEpiStars) * 4 * sizeof(double));
   L.status = take(sizeof(int));
   L.dpart = take(nb * 10 * sizeof(double));
   L.out8 = take(8 * sizeof(double));
@@ -106,12 +127,13 @@ struct GraphKey {
   const void *pos = nullptr, *vel = nullptr, *mass = nullptr;
   int64_t N = 0;
   double G = 0, c = 0, eps = 0, dt = 0;
-  int precision = -1, ipt = 0, nsplit = 0;
+  int precision = -1, ipt = 0, ws = 0, nsplit = 0;
   char* base = nullptr;
   bool operator==(const GraphKey& o) const {
     return pos == o.pos && vel == o.vel && mass == o.mass && N == o.N && G == o.G &&
            (c == o.c || (std::isinf(c) && std::isinf(o.c))) && eps == o.eps && dt == o.dt &&
-           precision == o.precision && ipt == o.ipt && nsplit == o.nsplit && base == o.base;
+           precision == o.precision && ipt == o.ipt && ws == o.ws && nsplit == o.nsplit &&
+           base == o.base;
   }
 };
 
@@ -219,10 +241,17 @@ int launch_prologue(const Sys& s, const Ptrs& P, int precision, hipStream_t st) 
 template <typename T, int MODE>
 void launch_pair_t(const PairArgs& a, const Shape& sh, hipStream_t st) {
   dim3 grid(sh.iblocks, sh.nsplit);
-  if (sh.ipt == 2)
-    hipLaunchKernelGGL((k_pair<T, MODE, 2>), grid, dim3(kBlock), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_pair<T, MODE, 1>), grid, dim3(kBlock), 0, st, a);
+  if (sh.ws == 4) {
+    if (sh.ipt == 2)
+      hipLaunchKernelGGL((k_pair<T, MODE, 2, 4>), grid, dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_pair<T, MODE, 1, 4>), grid, dim3(kBlock), 0, st, a);
+  } else {
+    if (sh.ipt == 2)
+      hipLaunchKernelGGL((k_pair<T, MODE, 2, 1>), grid, dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_pair<T, MODE, 1, 1>), grid, dim3(kBlock), 0, st, a);
+  }
 }
 
 int launch_pair(const Sys& s, const Ptrs& P, const Shape& sh, int precision, int mode,
@@ -260,7 +289,8 @@ struct Outs {
 
 int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o, hipStream_t st) {
   const int Ns = (int)(s.N - 1);
-  const int nb = (Ns + kBlock - 1) / kBlock;
+  const int nb = (Ns + kBlock - 1) / kBlock;            // prologue workgroups
+  const int ne = (Ns + kEpiStars - 1) / kEpiStars;      // epilogue workgroups
   EpiArgs a;
   a.pos = s.pos;
   a.vel = s.vel;
@@ -281,7 +311,7 @@ int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o,
   a.phi = o.phi;
   a.acc_1pn = o.acc_1pn;
   a.bhpart = P.at<double>(P.L.bhpart);
-  a.nbepi = nb;
+  a.nbepi = ne;
   a.status = P.at<int>(P.L.status);
   a.stage = o.stage;
   a.dt = o.dt;
@@ -291,7 +321,7 @@ int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o,
   a.Vs = o.Vs;
   a.KX = o.KX;
   a.KV = o.KV;
-  hipLaunchKernelGGL(k_epilogue, dim3(nb), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(k_epilogue, dim3(ne), dim3(kBlock), 0, st, a);
   HIPCK(hipGetLastError());
   hipLaunchKernelGGL(k_bh_final, dim3(1), dim3(kBlock), 0, st, a);
   HIPCK(hipGetLastError());
@@ -521,6 +551,7 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
       key.dt = dt;
       key.precision = precision;
       key.ipt = sh.ipt;
+      key.ws = sh.ws;
       key.nsplit = sh.nsplit;
       key.base = d->base;
       if (!d->gexec || !(key == d->key)) {
@@ -617,6 +648,19 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
   int rc = dev_state(&d);
   if (rc) return rc;
   HIPCK(hipStreamSynchronize(pick_stream(*d, stream)));
+  return PN_OK;
+}
+
+int pn_set_shape(int precision, int64_t n_min, int64_t n_max, int ipt, int ws, int nsplit) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (precision < 0) {
+    g_tuned.clear();
+    return PN_OK;
+  }
+  if ((precision != PN_FP64 && precision != PN_MIXED) || n_min < 2 || n_max < n_min ||
+      (ipt != 1 && ipt != 2) || (ws != 1 && ws != 4) || nsplit < 0 || nsplit > 65535)
+    return PN_EINVAL;
+  g_tuned.push_back(TunedShape{precision, n_min, n_max, ipt, ws, nsplit});
   return PN_OK;
 }
 

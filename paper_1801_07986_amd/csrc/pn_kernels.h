@@ -13,7 +13,7 @@
 //                         U_i  = sum_j G m_j / R_ij                (potential)
 //                         G_i  = sum_j G m_j x_ij / R_ij^3         (= -g_i)
 //                         Q_i  = sum_j (G m_j/R^3)[S'_ij x_ij - D'_ij v_j]
-//                         C2_i = sum_j (G m_j/R^3) D'_ij
+//                         C2_i = sum_j (G m_j/R^3) D'_ij        (stored / sqrt(3/2))
 //                         Q7_i = sum_j (G m_j/R) (-b_j / 2)
 //                       with S'_ij = e_j + 4 v_i.v_j + 3/2 (x_ij.v_j/R)^2
 //                       - x_ij.b_j/2, e_j = -2 v_j^2 + u_j, and
@@ -40,13 +40,20 @@ enum Field { F_U = 0, F_G = 1, F_Q = 4, F_C2 = 7, F_Q7 = 8 };
 enum PairMode { MODE_P1 = 1, MODE_P2 = 2, MODE_FUSED = 3 };
 
 // Star packet read by the pair sweep.  Positions stay FP64 so that coordinate
-// differences are formed in FP64 in both precisions.
+// differences are formed in FP64 in both precisions.  The velocity is stored
+// scaled, s = sqrt(3/2) v: then 3/2 (x.v_j / R)^2 = (x.s_j / R)^2, and with
+// the per-i vector (4/sqrt(3/2)) v_i the other velocity products come out
+// unscaled (4 v_i.v_j = [(4/sqrt(3/2)) v_i].s_j); D'_ij / sqrt(3/2) is
+// accumulated and rescaled in the epilogue.
+constexpr double kSqrt32 = 1.22474487139158904909864203735;    // sqrt(3/2)
+constexpr double kInvSqrt32 = 0.816496580927726032732428024902; // 1/sqrt(3/2)
+
 struct alignas(16) PkF64 {
-  double x, y, z, gm, vx, vy, vz, e, hbx, hby, hbz, pad;
+  double x, y, z, gm, svx, svy, svz, e, hbx, hby, hbz, pad;
 };
 struct alignas(16) PkF32 {
   double x, y, z;
-  float gm, vx, vy, vz, e, hbx, hby, hbz, pad0, pad1;
+  float gm, svx, svy, svz, e, hbx, hby, hbz, pad0, pad1;
 };
 static_assert(sizeof(PkF64) == 96, "packet layout");
 static_assert(sizeof(PkF32) == 64, "packet layout");
@@ -70,6 +77,16 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt_f64(x); }
 
+// a*b + c with c wavefront-uniform (held in SGPRs).  For doubles the compiler
+// otherwise copies c into a VGPR pair (two v_mov) to use the accumulating
+// v_fmac form; one VOP3 v_fma_f64 with a scalar addend is the same operation.
+__device__ __forceinline__ double fma_uniform_c(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+__device__ __forceinline__ float fma_uniform_c(float a, float b, float c) { return fmaf(a, b, c); }
+
 // Fixed-order workgroup sum of K doubles per thread; result in lds[k*kBlock].
 template <int K>
 __device__ __forceinline__ void block_sum(const double (&v)[K], double* lds) {
@@ -85,6 +102,10 @@ __device__ __forceinline__ void block_sum(const double (&v)[K], double* lds) {
     __syncthreads();
   }
 }
+
+// Wave index as a scalar (so that loop bounds derived from it stay uniform
+// and j packets keep coming through scalar loads).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Sum of `rows` partial rows of width `stride` (first K columns), fixed order:
 // thread t sums rows t, t+kBlock, ..., then a tree.  Same result in every block.
@@ -152,9 +173,9 @@ __global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
     p.y = ys;
     p.z = zs;
     p.gm = (T)(a.G * m);
-    p.vx = (T)vx;
-    p.vy = (T)vy;
-    p.vz = (T)vz;
+    p.svx = (T)(kSqrt32 * vx);
+    p.svy = (T)(kSqrt32 * vy);
+    p.svz = (T)(kSqrt32 * vz);
     p.e = (T)fma(-2.0, v2, u);
     p.hbx = (T)(-0.5 * bx);
     p.hby = (T)(-0.5 * by);
@@ -190,13 +211,15 @@ __global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Star-star sweep.  i-bodies live in registers (IPT per thread); every lane of
-// a wavefront visits the same j at the same time, so the j packet is uniform
-// and is read through the scalar unit into SGPRs (no LDS traffic, no
-// per-lane broadcast).  The j range of a workgroup is one of gridDim.y
-// splits; partial sums go to part[split][field][star].
+// Star-star sweep.  i-bodies live in registers (IPT per lane); every lane of a
+// wavefront visits the same j at the same time, so the j packet is uniform and
+// is read through the scalar unit into SGPRs (no LDS traffic, no per-lane
+// broadcast).  A workgroup owns the i-range [ilo, ihi) and the j-range of one
+// split (gridDim.y splits); with WS = 4 its four wavefronts share the i-range
+// and divide the split's j-range into four pieces, reduced in LDS in fixed
+// order at the end.  Partial sums go to part[split][field][star].
 // T = double: FP64 throughout.  T = float: FP64 coordinate differences, FP32
-// pair arithmetic, FP32 partial sums over tiles of kTile j, added into FP64
+// pair arithmetic, FP32 partial sums over tiles of kTile j added into FP64
 // accumulators after each tile.
 // ---------------------------------------------------------------------------
 struct PairArgs {
@@ -209,7 +232,7 @@ struct PairArgs {
 
 constexpr int kTile = 64;  // j per FP32 partial-sum tile (mixed precision)
 
-template <typename T, int MODE, int IPT>
+template <typename T, int IPT>
 struct PairAcc {
   T U[IPT], Gx[IPT], Gy[IPT], Gz[IPT], Qx[IPT], Qy[IPT], Qz[IPT], C2[IPT], Q7x[IPT], Q7y[IPT],
       Q7z[IPT];
@@ -221,94 +244,139 @@ struct PairAcc {
   }
 };
 
+template <typename T, int IPT>
+struct PairI {  // the i-side operands of one lane
+  double x[IPT], y[IPT], z[IPT];
+  T kx[IPT], ky[IPT], kz[IPT];  // (4/sqrt(3/2)) v_i
+  int idx[IPT];
+};
+
+template <typename T, int MODE, int IPT, bool MASK>
+__device__ __forceinline__ void pair_one(const typename PkOf<T>::type& p, int j, T eps2,
+                                         const PairI<T, IPT>& I, PairAcc<T, IPT>& A) {
+  const double xj = p.x, yj = p.y, zj = p.z;
+  const T gm = p.gm;
+#pragma unroll
+  for (int ii = 0; ii < IPT; ++ii) {
+    const T dx = (T)(I.x[ii] - xj), dy = (T)(I.y[ii] - yj), dz = (T)(I.z[ii] - zj);
+    T rinv = rsqrt_t(fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2))));
+    if (MASK) rinv = (j == I.idx[ii]) ? T(0) : rinv;
+    const T rinv2 = rinv * rinv;
+    const T mr = gm * rinv;
+    const T mr3 = mr * rinv2;
+    if (MODE & MODE_P1) A.U[ii] += mr;
+    A.Gx[ii] = fma(mr3, dx, A.Gx[ii]);
+    A.Gy[ii] = fma(mr3, dy, A.Gy[ii]);
+    A.Gz[ii] = fma(mr3, dz, A.Gz[ii]);
+    if (MODE & MODE_P2) {
+      const T sx = p.svx, sy = p.svy, sz = p.svz;  // sqrt(3/2) v_j
+      const T xs = fma(dz, sz, fma(dy, sy, dx * sx));
+      const T t = xs * rinv;
+      T s = fma_uniform_c(t, t, (T)p.e);           // e_j + 3/2 (x.v_j/R)^2
+      s = fma(I.kz[ii], sz, fma(I.ky[ii], sy, fma(I.kx[ii], sx, s)));  // + 4 v_i.v_j
+      s = fma(dz, (T)p.hbz, fma(dy, (T)p.hby, fma(dx, (T)p.hbx, s)));  // - x.b_j / 2
+      const T x4 = fma(dz, I.kz[ii], fma(dy, I.ky[ii], dx * I.kx[ii]));
+      const T D = fma(T(-2), xs, x4);              // x.(4 v_i - 3 v_j) / sqrt(3/2)
+      const T c1 = mr3 * s, c2 = mr3 * D;
+      A.Qx[ii] = fma(-c2, sx, fma(c1, dx, A.Qx[ii]));
+      A.Qy[ii] = fma(-c2, sy, fma(c1, dy, A.Qy[ii]));
+      A.Qz[ii] = fma(-c2, sz, fma(c1, dz, A.Qz[ii]));
+      A.C2[ii] += c2;
+      A.Q7x[ii] = fma(mr, (T)p.hbx, A.Q7x[ii]);
+      A.Q7y[ii] = fma(mr, (T)p.hby, A.Q7y[ii]);
+      A.Q7z[ii] = fma(mr, (T)p.hbz, A.Q7z[ii]);
+    }
+  }
+}
+
+// j loop with the next packet's scalar loads issued before the current
+// pair's arithmetic (software pipelining hides the load latency).
 template <typename T, int MODE, int IPT, bool MASK>
 __device__ __forceinline__ void pair_range(const typename PkOf<T>::type* __restrict__ pk, int j0,
-                                           int j1, T eps2, const double (&xi)[IPT],
-                                           const double (&yi)[IPT], const double (&zi)[IPT],
-                                           const T (&v4x)[IPT], const T (&v4y)[IPT],
-                                           const T (&v4z)[IPT], const int (&idx)[IPT],
-                                           PairAcc<T, MODE, IPT>& A) {
-#pragma unroll 2
+                                           int j1, T eps2, const PairI<T, IPT>& I,
+                                           PairAcc<T, IPT>& A) {
+  using Pk = typename PkOf<T>::type;
+  if (j0 >= j1) return;
+  Pk cur = pk[j0];
   for (int j = j0; j < j1; ++j) {
-    const auto& p = pk[j];
-    const double xj = p.x, yj = p.y, zj = p.z;
-    const T gm = p.gm;
-#pragma unroll
-    for (int ii = 0; ii < IPT; ++ii) {
-      const T dx = (T)(xi[ii] - xj), dy = (T)(yi[ii] - yj), dz = (T)(zi[ii] - zj);
-      T rinv = rsqrt_t(fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2))));
-      if (MASK) rinv = (j == idx[ii]) ? T(0) : rinv;
-      const T rinv2 = rinv * rinv;
-      const T mr = gm * rinv;
-      const T mr3 = mr * rinv2;
-      if (MODE & MODE_P1) A.U[ii] += mr;
-      A.Gx[ii] = fma(mr3, dx, A.Gx[ii]);
-      A.Gy[ii] = fma(mr3, dy, A.Gy[ii]);
-      A.Gz[ii] = fma(mr3, dz, A.Gz[ii]);
-      if (MODE & MODE_P2) {
-        const T vxj = p.vx, vyj = p.vy, vzj = p.vz;
-        const T xvj = fma(dz, vzj, fma(dy, vyj, dx * vxj));
-        const T x4vi = fma(dz, v4z[ii], fma(dy, v4y[ii], dx * v4x[ii]));
-        T s = fma(v4z[ii], vzj, fma(v4y[ii], vyj, fma(v4x[ii], vxj, (T)p.e)));
-        s = fma(dz, (T)p.hbz, fma(dy, (T)p.hby, fma(dx, (T)p.hbx, s)));
-        const T t = xvj * rinv;
-        s = fma(T(1.5) * t, t, s);
-        const T D = fma(T(-3), xvj, x4vi);
-        const T c1 = mr3 * s, c2 = mr3 * D;
-        A.Qx[ii] = fma(-c2, vxj, fma(c1, dx, A.Qx[ii]));
-        A.Qy[ii] = fma(-c2, vyj, fma(c1, dy, A.Qy[ii]));
-        A.Qz[ii] = fma(-c2, vzj, fma(c1, dz, A.Qz[ii]));
-        A.C2[ii] += c2;
-        A.Q7x[ii] = fma(mr, (T)p.hbx, A.Q7x[ii]);
-        A.Q7y[ii] = fma(mr, (T)p.hby, A.Q7y[ii]);
-        A.Q7z[ii] = fma(mr, (T)p.hbz, A.Q7z[ii]);
-      }
-    }
+    const Pk nxt = pk[min(j + 1, j1 - 1)];
+    pair_one<T, MODE, IPT, MASK>(cur, j, eps2, I, A);
+    cur = nxt;
   }
 }
 
 template <typename T, int MODE, int IPT>
 __device__ __forceinline__ void pair_segment(const typename PkOf<T>::type* __restrict__ pk, int j0,
                                              int j1, int ilo, int ihi, T eps2,
-                                             const double (&xi)[IPT], const double (&yi)[IPT],
-                                             const double (&zi)[IPT], const T (&v4x)[IPT],
-                                             const T (&v4y)[IPT], const T (&v4z)[IPT],
-                                             const int (&idx)[IPT], PairAcc<T, MODE, IPT>& A) {
+                                             const PairI<T, IPT>& I, PairAcc<T, IPT>& A) {
   // the diagonal j == i can only occur for j in [ilo, ihi)
   const int m0 = max(j0, ilo), m1 = min(j1, ihi);
   if (m0 < m1) {
-    pair_range<T, MODE, IPT, false>(pk, j0, m0, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
-    pair_range<T, MODE, IPT, true>(pk, m0, m1, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
-    pair_range<T, MODE, IPT, false>(pk, m1, j1, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
+    pair_range<T, MODE, IPT, false>(pk, j0, m0, eps2, I, A);
+    pair_range<T, MODE, IPT, true>(pk, m0, m1, eps2, I, A);
+    pair_range<T, MODE, IPT, false>(pk, m1, j1, eps2, I, A);
   } else {
-    pair_range<T, MODE, IPT, false>(pk, j0, j1, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
+    pair_range<T, MODE, IPT, false>(pk, j0, j1, eps2, I, A);
   }
 }
 
-template <typename T, int MODE, int IPT>
-__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
-  using Pk = typename PkOf<T>::type;
-  const Pk* __restrict__ pk = static_cast<const Pk*>(a.pk);
-  const int ilo = blockIdx.x * (kBlock * IPT);
-  const int ihi = min(a.Ns, ilo + kBlock * IPT);
-  double xi[IPT], yi[IPT], zi[IPT];
-  T v4x[IPT], v4y[IPT], v4z[IPT];
-  int idx[IPT];
+template <typename T, int IPT>
+__device__ __forceinline__ void acc_flush(const PairAcc<T, IPT>& A, double (&acc)[kNF][IPT]) {
 #pragma unroll
   for (int ii = 0; ii < IPT; ++ii) {
-    idx[ii] = ilo + threadIdx.x + ii * kBlock;
-    const int il = min(idx[ii], a.Ns - 1);  // lanes past the end compute on a copy, never stored
-    const Pk& p = pk[il];
-    xi[ii] = p.x;
-    yi[ii] = p.y;
-    zi[ii] = p.z;
-    v4x[ii] = T(4) * (T)p.vx;
-    v4y[ii] = T(4) * (T)p.vy;
-    v4z[ii] = T(4) * (T)p.vz;
+    acc[F_U][ii] += (double)A.U[ii];
+    acc[F_G][ii] += (double)A.Gx[ii];
+    acc[F_G + 1][ii] += (double)A.Gy[ii];
+    acc[F_G + 2][ii] += (double)A.Gz[ii];
+    acc[F_Q][ii] += (double)A.Qx[ii];
+    acc[F_Q + 1][ii] += (double)A.Qy[ii];
+    acc[F_Q + 2][ii] += (double)A.Qz[ii];
+    acc[F_C2][ii] += (double)A.C2[ii];
+    acc[F_Q7][ii] += (double)A.Q7x[ii];
+    acc[F_Q7 + 1][ii] += (double)A.Q7y[ii];
+    acc[F_Q7 + 2][ii] += (double)A.Q7z[ii];
   }
-  const int split = blockIdx.y;
-  const int j0 = split * a.jchunk;
-  const int j1 = min(a.Ns, j0 + a.jchunk);
+}
+
+__device__ __forceinline__ bool field_written(int f, int mode) {
+  if (f == F_U) return (mode & MODE_P1) != 0;
+  if (f < F_Q) return true;
+  return (mode & MODE_P2) != 0;
+}
+
+template <typename T, int MODE, int IPT, int WS>
+__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
+  using Pk = typename PkOf<T>::type;
+  constexpr int LANES = kBlock / WS;  // distinct i-lanes per workgroup
+  constexpr int IB = LANES * IPT;     // i-bodies per workgroup
+  const Pk* __restrict__ pk = static_cast<const Pk*>(a.pk);
+  const int wave = WS > 1 ? wave_id() : 0;
+  const int lane = WS > 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  const int ilo = blockIdx.x * IB;
+  const int ihi = min(a.Ns, ilo + IB);
+  PairI<T, IPT> I;
+#pragma unroll
+  for (int ii = 0; ii < IPT; ++ii) {
+    I.idx[ii] = ilo + lane + ii * LANES;
+    const int il = min(I.idx[ii], a.Ns - 1);  // lanes past the end compute on a copy, never stored
+    const Pk& p = pk[il];
+    I.x[ii] = p.x;
+    I.y[ii] = p.y;
+    I.z[ii] = p.z;
+    // (4/sqrt(3/2)) v_i = (8/3) s_i
+    I.kx[ii] = T(8.0 / 3.0) * (T)p.svx;
+    I.ky[ii] = T(8.0 / 3.0) * (T)p.svy;
+    I.kz[ii] = T(8.0 / 3.0) * (T)p.svz;
+  }
+  // j-range of this wavefront
+  int j0 = blockIdx.y * a.jchunk;
+  int j1 = min(a.Ns, j0 + a.jchunk);
+  if (WS > 1) {
+    const int q = (j1 - j0 + WS - 1) / WS;
+    const int w0 = min(j1, j0 + wave * q);
+    j1 = min(j1, w0 + q);
+    j0 = w0;
+  }
   const T eps2 = (T)a.eps2;
 
   double acc[kNF][IPT];
@@ -317,60 +385,49 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
 #pragma unroll
     for (int ii = 0; ii < IPT; ++ii) acc[f][ii] = 0.0;
 
-  PairAcc<T, MODE, IPT> A;
+  PairAcc<T, IPT> A;
   if constexpr (sizeof(T) == 8) {
     A.zero();
-    pair_segment<T, MODE, IPT>(pk, j0, j1, ilo, ihi, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
-#pragma unroll
-    for (int ii = 0; ii < IPT; ++ii) {
-      acc[F_U][ii] = A.U[ii];
-      acc[F_G][ii] = A.Gx[ii];
-      acc[F_G + 1][ii] = A.Gy[ii];
-      acc[F_G + 2][ii] = A.Gz[ii];
-      acc[F_Q][ii] = A.Qx[ii];
-      acc[F_Q + 1][ii] = A.Qy[ii];
-      acc[F_Q + 2][ii] = A.Qz[ii];
-      acc[F_C2][ii] = A.C2[ii];
-      acc[F_Q7][ii] = A.Q7x[ii];
-      acc[F_Q7 + 1][ii] = A.Q7y[ii];
-      acc[F_Q7 + 2][ii] = A.Q7z[ii];
-    }
+    pair_segment<T, MODE, IPT>(pk, j0, j1, ilo, ihi, eps2, I, A);
+    acc_flush<T, IPT>(A, acc);
   } else {
     for (int t0 = j0; t0 < j1; t0 += kTile) {
       const int t1 = min(j1, t0 + kTile);
       A.zero();
-      pair_segment<T, MODE, IPT>(pk, t0, t1, ilo, ihi, eps2, xi, yi, zi, v4x, v4y, v4z, idx, A);
-#pragma unroll
-      for (int ii = 0; ii < IPT; ++ii) {
-        acc[F_U][ii] += (double)A.U[ii];
-        acc[F_G][ii] += (double)A.Gx[ii];
-        acc[F_G + 1][ii] += (double)A.Gy[ii];
-        acc[F_G + 2][ii] += (double)A.Gz[ii];
-        if (MODE & MODE_P2) {
-          acc[F_Q][ii] += (double)A.Qx[ii];
-          acc[F_Q + 1][ii] += (double)A.Qy[ii];
-          acc[F_Q + 2][ii] += (double)A.Qz[ii];
-          acc[F_C2][ii] += (double)A.C2[ii];
-          acc[F_Q7][ii] += (double)A.Q7x[ii];
-          acc[F_Q7 + 1][ii] += (double)A.Q7y[ii];
-          acc[F_Q7 + 2][ii] += (double)A.Q7z[ii];
-        }
-      }
+      pair_segment<T, MODE, IPT>(pk, t0, t1, ilo, ihi, eps2, I, A);
+      acc_flush<T, IPT>(A, acc);
     }
   }
 
   const size_t plane = (size_t)a.Ns;
-  double* out = a.part + (size_t)split * kNF * plane;
+  double* out = a.part + (size_t)blockIdx.y * kNF * plane;
+  if constexpr (WS == 1) {
 #pragma unroll
-  for (int ii = 0; ii < IPT; ++ii) {
-    if (idx[ii] < a.Ns) {
-      if (MODE & MODE_P1) out[F_U * plane + idx[ii]] = acc[F_U][ii];
-      out[(F_G + 0) * plane + idx[ii]] = acc[F_G][ii];
-      out[(F_G + 1) * plane + idx[ii]] = acc[F_G + 1][ii];
-      out[(F_G + 2) * plane + idx[ii]] = acc[F_G + 2][ii];
-      if (MODE & MODE_P2) {
+    for (int ii = 0; ii < IPT; ++ii) {
+      if (I.idx[ii] < a.Ns) {
 #pragma unroll
-        for (int f = F_Q; f < kNF; ++f) out[f * plane + idx[ii]] = acc[f][ii];
+        for (int f = 0; f < kNF; ++f)
+          if (field_written(f, MODE)) out[f * plane + I.idx[ii]] = acc[f][ii];
+      }
+    }
+  } else {
+    // fixed-order reduction over the WS wavefronts
+    __shared__ double red[WS * kNF * IPT * 64];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f)
+#pragma unroll
+      for (int ii = 0; ii < IPT; ++ii) red[((wave * kNF + f) * IPT + ii) * 64 + lane] = acc[f][ii];
+    __syncthreads();
+    for (int v = threadIdx.x; v < kNF * IPT * 64; v += kBlock) {
+      const int f = v / (IPT * 64);
+      const int ii = (v / 64) % IPT;
+      const int l = v & 63;
+      const int idx = ilo + l + ii * 64;
+      if (idx < a.Ns && field_written(f, MODE)) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < WS; ++w) sum += red[((w * kNF + f) * IPT + ii) * 64 + l];
+        out[f * plane + idx] = sum;
       }
     }
   }
@@ -460,8 +517,17 @@ __device__ __forceinline__ void bh_quantities(const EpiArgs& a, double* lds, dou
   }
 }
 
+constexpr int kEpiStars = 64;  // stars per epilogue workgroup (4 threads per star reduce the splits)
+
+__device__ __forceinline__ bool epi_field_used(int f, const EpiArgs& a) {
+  if (f == F_U) return a.phi_in == nullptr;  // correction mode: U is not computed
+  if (f < F_Q) return true;
+  return !a.newton_only;
+}
+
 __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   __shared__ double lds[7 * kBlock];
+  __shared__ double fsum[kNF * kEpiStars];
   double A0[3], V0, P[3];
   bh_quantities(a, lds, A0, V0, P);
   const double M = a.mass[0];
@@ -469,25 +535,31 @@ __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   const double w[3] = {-P[0] / M, -P[1] / M, -P[2] / M};
   const double x0 = a.pos[0], y0 = a.pos[1], z0 = a.pos[2];
 
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  double bh[3] = {0.0, 0.0, 0.0};
-  if (k < a.Ns) {
-    const int i = k + 1;
-    const size_t plane = (size_t)a.Ns;
-    double sum[kNF];
-#pragma unroll
-    for (int f = 0; f < kNF; ++f) sum[f] = 0.0;
-    for (int sp = 0; sp < a.nsplit; ++sp) {
-      const double* pp = a.part + (size_t)sp * kNF * plane + k;
-      if (!a.phi_in) sum[F_U] += pp[F_U * plane];  // not computed in correction mode
-      sum[F_G] += pp[F_G * plane];
-      sum[F_G + 1] += pp[(F_G + 1) * plane];
-      sum[F_G + 2] += pp[(F_G + 2) * plane];
-      if (!a.newton_only) {
-#pragma unroll
-        for (int f = F_Q; f < kNF; ++f) sum[f] += pp[f * plane];
+  // split reduction: thread (g, l) sums fields g, g+4, g+8 of star l, in split order
+  {
+    const int g = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int k = blockIdx.x * kEpiStars + l;
+    if (k < a.Ns) {
+      const size_t plane = (size_t)a.Ns;
+      for (int f = g; f < kNF; f += 4) {
+        double sum = 0.0;
+        if (epi_field_used(f, a)) {
+          for (int sp = 0; sp < a.nsplit; ++sp) sum += a.part[((size_t)sp * kNF + f) * plane + k];
+        }
+        fsum[f * kEpiStars + l] = sum;
       }
     }
+  }
+  __syncthreads();
+
+  const int k = blockIdx.x * kEpiStars + threadIdx.x;
+  double bh[3] = {0.0, 0.0, 0.0};
+  if (threadIdx.x < kEpiStars && k < a.Ns) {
+    const int i = k + 1;
+    double sum[kNF];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f) sum[f] = fsum[f * kEpiStars + threadIdx.x];
+    sum[F_C2] *= kSqrt32;  // the sweep accumulates D'/sqrt(3/2)
     const double* ub = a.ub + 4 * (size_t)k;
     const double ui = ub[0], bx = ub[1], by = ub[2], bz = ub[3];
     // Newtonian part: g_i - b_i with g_i = -G_i
@@ -624,7 +696,8 @@ __global__ __launch_bounds__(kBlock) void k_diag_pair(DiagPairArgs a) {
   const int ihi = min(a.Ns, ilo + kBlock);
   const int i = ilo + threadIdx.x;
   const PkF64& pi = pk[min(i, a.Ns - 1)];
-  const double xi = pi.x, yi = pi.y, zi = pi.z, vxi = pi.vx, vyi = pi.vy, vzi = pi.vz;
+  const double xi = pi.x, yi = pi.y, zi = pi.z;
+  const double vxi = kInvSqrt32 * pi.svx, vyi = kInvSqrt32 * pi.svy, vzi = kInvSqrt32 * pi.svz;
   const int j0 = blockIdx.y * a.jchunk, j1 = min(a.Ns, j0 + a.jchunk);
   double U = 0.0, W = 0.0, Yx = 0.0, Yy = 0.0, Yz = 0.0;
   for (int j = j0; j < j1; ++j) {
@@ -634,9 +707,10 @@ __global__ __launch_bounds__(kBlock) void k_diag_pair(DiagPairArgs a) {
     if (j >= ilo && j < ihi) rinv = (j == i) ? 0.0 : rinv;
     const double mr = p.gm * rinv;
     const double rinv2 = rinv * rinv;
-    const double vv = fma(vzi, p.vz, fma(vyi, p.vy, vxi * p.vx));
+    const double vxj = kInvSqrt32 * p.svx, vyj = kInvSqrt32 * p.svy, vzj = kInvSqrt32 * p.svz;
+    const double vv = fma(vzi, vzj, fma(vyi, vyj, vxi * vxj));
     const double xvi = fma(dz, vzi, fma(dy, vyi, dx * vxi));
-    const double xvj = fma(dz, p.vz, fma(dy, p.vy, dx * p.vx));
+    const double xvj = fma(dz, vzj, fma(dy, vyj, dx * vxj));
     U += mr;
     W = fma(mr, fma(-xvi * xvj, rinv2, -7.0 * vv), W);
     const double cy = mr * xvi * rinv2;
