@@ -133,6 +133,7 @@ def main() -> int:
 
     if not args.no_secondary:
         result["secondary"] = secondary(pn, torch, inputs, stream)
+        result["ensemble"] = ensemble(pn, torch, inputs, stream)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(pos0, vel0, mass0, G, c, eps)
@@ -160,6 +161,56 @@ def secondary(pn, torch, inputs, stream):
         out[name + "_pair_per_s"] = 4.0 * 10 * N * N / dt_wall
         log(f"secondary N={N} {name}: {out[name + '_pair_per_s']:.4e} pair/s")
     out["mixed_over_fp64"] = out["mixed_pair_per_s"] / out["fp64_pair_per_s"]
+    return out
+
+
+def ensemble(pn, torch, inputs, stream, steps=2):
+    """256 independent Plummer + black-hole systems, N ~ U{1024..16384},
+    M_bh ~ U[0.01, 0.1], c ~ U[20, 100]: pn_step_batched (one launch per phase
+    for all systems, graph-captured step) vs the same systems stepped one
+    after another with pn_step, FP64 and mixed."""
+    systems = inputs.ensemble()
+    ps, vs, ms, off = [], [], [], [0]
+    for s in systems:
+        p, v, m = inputs.plummer_bh(s["N"], s["M_bh"], s["seed"])
+        ps.append(p)
+        vs.append(v)
+        ms.append(m)
+        off.append(off[-1] + s["N"])
+    pos0, vel0, mass0 = np.concatenate(ps), np.concatenate(vs), np.concatenate(ms)
+    Gs = [1.0] * len(systems)
+    cs = [s["c"] for s in systems]
+    es = [s["eps"] for s in systems]
+    pairs = 4.0 * steps * sum(float(s["N"]) ** 2 for s in systems)
+    out = {"workload": "ensemble256", "n_sys": len(systems), "bodies": int(off[-1]),
+           "steps": steps, "pairs_per_step": pairs / steps}
+    for name, prec in (("fp64", pn.PN_FP64), ("mixed", pn.PN_MIXED)):
+        pos = torch.from_numpy(pos0).cuda()
+        vel = torch.from_numpy(vel0).cuda()
+        mass = torch.from_numpy(mass0).cuda()
+        pn.pn_step_batched(off, Gs, cs, es, pos, vel, mass, 1e-4, 1, prec, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pn.pn_step_batched(off, Gs, cs, es, pos, vel, mass, 1e-4, steps, prec, stream=stream)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        out[f"batched_{name}_pair_per_s"] = pairs / tb
+        log(f"ensemble batched {name}: {pairs / tb:.4e} pair/s")
+        views = [(pos[off[k]:off[k + 1]], vel[off[k]:off[k + 1]], mass[off[k]:off[k + 1]])
+                 for k in range(len(systems))]
+        for k, (p, v, m) in enumerate(views):  # warm every system's graph
+            pn.pn_step(p, v, m, 1.0, cs[k], es[k], 1e-4, 1, prec, stream=stream,
+                       flags=pn.PN_ASYNC | pn.PN_NOGRAPH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, (p, v, m) in enumerate(views):
+            pn.pn_step(p, v, m, 1.0, cs[k], es[k], 1e-4, steps, prec, stream=stream,
+                       flags=pn.PN_ASYNC | pn.PN_NOGRAPH)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        out[f"sequential_{name}_pair_per_s"] = pairs / ts
+        out[f"batched_over_sequential_{name}"] = ts / tb
+        log(f"ensemble sequential {name}: {pairs / ts:.4e} pair/s")
     return out
 
 

@@ -106,6 +106,18 @@ int pn_accel(const double* pos, const double* vel, const double* mass, int64_t N
              double* acc_1pn, void* stream, int flags);
 
 /*
+ * Unrestricted EIH 1PN accelerations of all N bodies: every pair at full 1PN
+ * order, with no body singled out (the general N-body 1PN equations the paper
+ * starts from in Sec. 2 and names as its next step in Sec. 5).  Evaluated in
+ * two O(N^2) sweeps: the Newtonian potential and acceleration of every body,
+ * then the 1PN pair sum, which uses them.  Same softening reading and output
+ * layout as pn_accel; every body's own velocity enters (vel[0] included).
+ */
+int pn_accel_eih(const double* pos, const double* vel, const double* mass, int64_t N, double G,
+                 double c, double eps, int precision, double* acc_newton, double* phi,
+                 double* acc_1pn, void* stream, int flags);
+
+/*
  * Advance (pos, vel) of all N bodies, massive object included, by nsteps
  * fixed steps of the classical fourth-order Runge-Kutta method (Sec. 3.2 and
  * Sec. 4): four force evaluations per step, f(x, v) = (v, a^N + a^1PN).

@@ -55,6 +55,8 @@ def _load():
                               ctypes.c_double, _dp],
             "pnref_eih": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
                           ctypes.c_double, _dp, _dp],
+            "pnref_eih2": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_double, _dp, _dp, _dp],
             "pnref_twobody": [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, _dp, _dp],
             "pnref_step": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
@@ -147,6 +149,16 @@ def eih(pos, vel, mass, G, c, eps):
     _check(_load().pnref_eih(_p(pos), _p(vel), _p(mass), N, G, c, eps, _p(aN), _p(a1)),
            "pnref_eih")
     return aN, a1
+
+
+def eih2(pos, vel, mass, G, c, eps):
+    """Unrestricted EIH, potentials summed once: (acc_newton, phi, lambda * 1PN part)."""
+    N = len(mass)
+    pos, vel, mass = _arr(pos, (N, 3)), _arr(vel, (N, 3)), _arr(mass, (N,))
+    aN, phi, a1 = np.empty((N, 3)), np.empty(N), np.empty((N, 3))
+    _check(_load().pnref_eih2(_p(pos), _p(vel), _p(mass), N, G, c, eps, _p(aN), _p(phi), _p(a1)),
+           "pnref_eih2")
+    return aN, phi, a1
 
 
 def twobody(x, v, m1, m2, G, c):

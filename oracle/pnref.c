@@ -593,6 +593,45 @@ int pnref_eih(const double *pos, const double *vel, const double *mass, idx_t N,
 }
 
 /* ------------------------------------------------------------------ */
+/* The same unrestricted EIH equations with each body's potential V_b  */
+/* and Newtonian acceleration a^N_b summed once beforehand (O(N^2)):    */
+/* the definition above, not regrouped.  Writes a^N, phi = -V and the   */
+/* 1PN part (times lambda) of every body.                               */
+/* ------------------------------------------------------------------ */
+int pnref_eih2(const double *pos, const double *vel, const double *mass, idx_t N, double G,
+               double c, double eps, double *acc_newton, double *phi, double *acc_1pn) {
+  int rc = check_common(pos, mass, N, G, eps);
+  if (rc) return rc;
+  if (check_c(c) || !vel || !acc_newton || !phi || !acc_1pn) return PNREF_EINVAL;
+  rc = pnref_newton(pos, mass, N, G, eps, acc_newton, phi);
+  if (rc) return rc;
+  const double lam = lambda_of(c);
+  const double eps2 = eps * eps;
+#pragma omp parallel for schedule(static)
+  for (idx_t a = 0; a < N; ++a) {
+    const double *xa = pos + 3 * a, *va = vel + 3 * a;
+    const double Va = -phi[a];
+    double pn[3] = {0, 0, 0};
+    for (idx_t b = 0; b < N; ++b) {
+      if (b == a) continue;
+      const double *xb = pos + 3 * b, *vb = vel + 3 * b, *aNb = acc_newton + 3 * b;
+      double xab[3];
+      double R = sep(xa, xb, eps2, xab);
+      double n[3] = {xab[0] / R, xab[1] / R, xab[2] / R};
+      double nvb = dot3(n, vb);
+      double br = -dot3(va, va) - 2.0 * dot3(vb, vb) + 4.0 * dot3(va, vb) + 1.5 * nvb * nvb +
+                  4.0 * Va - phi[b] + 0.5 * dot3(xab, aNb);
+      double D = 4.0 * dot3(n, va) - 3.0 * nvb;
+      double k = G * mass[b] / (R * R);
+      for (int q = 0; q < 3; ++q)
+        pn[q] += k * br * n[q] + k * D * (va[q] - vb[q]) + 3.5 * (G * mass[b] / R) * aNb[q];
+    }
+    for (int q = 0; q < 3; ++q) acc_1pn[3 * a + q] = lam * pn[q];
+  }
+  return PNREF_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Textbook two-body 1PN relative acceleration in harmonic gauge (the  */
 /* N = 2 case of the EIH equations the paper cites):                   */
 /*   a = -(G m / r^2) [ (1 + lambda A) n + lambda B v ]                  */

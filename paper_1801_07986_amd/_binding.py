@@ -19,7 +19,8 @@ PN_FP64, PN_MIXED = 0, 1
 PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
 
 EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
-           "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape")
+           "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape",
+           "pn_accel_eih")
 TUNED_PATH = os.path.join(HERE, "tuned_shapes.json")
 
 
@@ -44,6 +45,7 @@ def load():
         lib.pn_potential_accel.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, i32]
         lib.pn_correction.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, vp, i32]
         lib.pn_accel.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
+        lib.pn_accel_eih.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
         lib.pn_step.argtypes = [vp, vp, vp, i64, d, d, d, d, i64, i32, vp, i32]
         lib.pn_diagnostics.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, i32]
         lib.pn_step_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, d, i64, i32,
@@ -128,6 +130,13 @@ def pn_accel(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None, ac
     return _check(load().pn_accel(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
                                   precision, _ptr(acc_newton), _ptr(phi), _ptr(acc_1pn),
                                   _stream(stream), flags), "pn_accel")
+
+
+def pn_accel_eih(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None, acc_1pn=None,
+                 stream=None, flags=0):
+    return _check(load().pn_accel_eih(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
+                                      precision, _ptr(acc_newton), _ptr(phi), _ptr(acc_1pn),
+                                      _stream(stream), flags), "pn_accel_eih")
 
 
 def pn_step(pos, vel, mass, G, c, eps, dt, nsteps, precision=PN_FP64, stream=None, flags=0):

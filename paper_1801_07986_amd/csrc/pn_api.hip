@@ -137,6 +137,20 @@ struct GraphKey {
   }
 };
 
+struct BatchKey {
+  std::vector<int64_t> offsets;
+  std::vector<double> G, c, eps;
+  const void *pos = nullptr, *vel = nullptr, *mass = nullptr;
+  double dt = 0;
+  int precision = -1;
+  char* base = nullptr;
+  bool operator==(const BatchKey& o) const {
+    return offsets == o.offsets && G == o.G && c == o.c && eps == o.eps && pos == o.pos &&
+           vel == o.vel && mass == o.mass && dt == o.dt && precision == o.precision &&
+           base == o.base;
+  }
+};
+
 struct DevState {
   bool init = false;
   hipStream_t own = nullptr;
@@ -146,6 +160,12 @@ struct DevState {
   hipGraphExec_t gexec = nullptr;
   GraphKey key;
   std::vector<hipEvent_t> ev;
+  // batched ensembles: own scratch and step graph
+  char* bbase = nullptr;
+  size_t bcap = 0;
+  hipGraph_t bgraph = nullptr;
+  hipGraphExec_t bgexec = nullptr;
+  BatchKey bkey;
 };
 std::vector<DevState> g_dev;
 
@@ -170,6 +190,27 @@ void drop_graph(DevState& d) {
   d.gexec = nullptr;
   d.graph = nullptr;
   d.key = GraphKey();
+}
+
+void drop_batch_graph(DevState& d) {
+  if (d.bgexec) hipGraphExecDestroy(d.bgexec);
+  if (d.bgraph) hipGraphDestroy(d.bgraph);
+  d.bgexec = nullptr;
+  d.bgraph = nullptr;
+  d.bkey = BatchKey();
+}
+
+int ensure_batch_scratch(DevState& d, size_t bytes) {
+  if (bytes <= d.bcap) return PN_OK;
+  HIPCK(hipDeviceSynchronize());
+  drop_batch_graph(d);
+  if (d.bbase) HIPCK(hipFree(d.bbase));
+  d.bbase = nullptr;
+  d.bcap = 0;
+  hipError_t e = hipMalloc(&d.bbase, bytes);
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(batched scratch)", __LINE__);
+  d.bcap = bytes;
+  return PN_OK;
 }
 
 int ensure_scratch(DevState& d, size_t bytes) {
@@ -423,6 +464,141 @@ hipStream_t pick_stream(DevState& d, void* stream) {
   return stream ? reinterpret_cast<hipStream_t>(stream) : d.own;
 }
 
+// ------------------------------------------------------------------ batched ensembles
+struct BatchPlan {
+  std::vector<SysDev> sys;
+  std::vector<int> order, pre_pro, pre_pair, pre_epi;
+  size_t o_sys, o_order, o_pre_pro, o_pre_pair, o_pre_epi, o_pk, o_ub, o_bpart, o_part, o_bhpart,
+      o_status, o_xs, o_vs, o_kx, o_kv, total;
+  int64_t n_bodies = 0;
+};
+
+// Shapes, partial-sum slots and launch prefixes of an ensemble.  Every
+// system uses the sweep shape (1 i per lane, 4 wavefronts per i-range); the
+// number of j-splits is common, chosen so the whole ensemble has ~16k sweep
+// workgroups, and capped so each wavefront keeps at least 32 j.
+BatchPlan plan_batch(int n_sys, const int64_t* off, const double* G, const double* c,
+                     const double* eps) {
+  BatchPlan P;
+  P.sys.resize(n_sys);
+  int64_t tot_iblocks = 0;
+  for (int b = 0; b < n_sys; ++b) tot_iblocks += (off[b + 1] - off[b] - 1 + 63) / 64;
+  const int ns_common =
+      (int)std::max<int64_t>(1, std::min<int64_t>(16, (16384 + tot_iblocks - 1) / tot_iblocks));
+  int64_t star0 = 0, part0 = 0;
+  int pro0 = 0, epi0 = 0;
+  for (int b = 0; b < n_sys; ++b) {
+    SysDev& S = P.sys[b];
+    const int Ns = (int)(off[b + 1] - off[b] - 1);
+    S.body0 = off[b];
+    S.star0 = star0;
+    S.part0 = part0;
+    S.Ns = Ns;
+    S.iblocks = (Ns + 63) / 64;
+    int ns = std::max(1, std::min(ns_common, Ns / 128));
+    S.jchunk = (Ns + ns - 1) / ns;
+    S.nsplit = (Ns + S.jchunk - 1) / S.jchunk;
+    S.npro = (Ns + kBlock - 1) / kBlock;
+    S.nepi = (Ns + kEpiStars - 1) / kEpiStars;
+    S.pro0 = pro0;
+    S.epi0 = epi0;
+    S.G = G[b];
+    S.lam = lambda_of(c[b]);
+    S.eps2 = eps[b] * eps[b];
+    star0 += Ns;
+    part0 += (int64_t)S.nsplit * kNF * Ns;
+    pro0 += S.npro;
+    epi0 += S.nepi;
+  }
+  P.n_bodies = off[n_sys];
+  P.order.resize(n_sys);
+  for (int b = 0; b < n_sys; ++b) P.order[b] = b;
+  std::stable_sort(P.order.begin(), P.order.end(),
+                   [&](int x, int y) { return P.sys[x].Ns > P.sys[y].Ns; });
+  P.pre_pro.assign(n_sys + 1, 0);
+  P.pre_pair.assign(n_sys + 1, 0);
+  P.pre_epi.assign(n_sys + 1, 0);
+  for (int r = 0; r < n_sys; ++r) {
+    const SysDev& S = P.sys[P.order[r]];
+    P.pre_pro[r + 1] = P.pre_pro[r] + S.npro;
+    P.pre_pair[r + 1] = P.pre_pair[r] + S.iblocks * S.nsplit;
+    P.pre_epi[r + 1] = P.pre_epi[r] + S.nepi;
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  P.o_sys = take(n_sys * sizeof(SysDev));
+  P.o_order = take(n_sys * sizeof(int));
+  P.o_pre_pro = take((n_sys + 1) * sizeof(int));
+  P.o_pre_pair = take((n_sys + 1) * sizeof(int));
+  P.o_pre_epi = take((n_sys + 1) * sizeof(int));
+  P.o_pk = take((size_t)star0 * sizeof(PkF64));
+  P.o_ub = take((size_t)star0 * 4 * sizeof(double));
+  P.o_bpart = take((size_t)pro0 * 8 * sizeof(double));
+  P.o_part = take((size_t)part0 * sizeof(double));
+  P.o_bhpart = take((size_t)epi0 * 4 * sizeof(double));
+  P.o_status = take(sizeof(int));
+  const size_t n3 = 3 * (size_t)P.n_bodies * sizeof(double);
+  P.o_xs = take(n3);
+  P.o_vs = take(n3);
+  P.o_kx = take(n3);
+  P.o_kv = take(n3);
+  P.total = o;
+  return P;
+}
+
+int enqueue_batched_step(const BatchPlan& P, char* base, const double* mass, double* X, double* V,
+                         double dt, int precision, hipStream_t st) {
+  const int n_sys = (int)P.sys.size();
+  BatchArgs b;
+  b.sys = reinterpret_cast<const SysDev*>(base + P.o_sys);
+  b.order = reinterpret_cast<const int*>(base + P.o_order);
+  b.n_sys = n_sys;
+  b.mass = mass;
+  b.pk = base + P.o_pk;
+  b.ub = reinterpret_cast<double*>(base + P.o_ub);
+  b.bpart = reinterpret_cast<double*>(base + P.o_bpart);
+  b.part = reinterpret_cast<double*>(base + P.o_part);
+  b.bhpart = reinterpret_cast<double*>(base + P.o_bhpart);
+  b.status = reinterpret_cast<int*>(base + P.o_status);
+  b.dt = dt;
+  b.X = X;
+  b.V = V;
+  b.Xs = reinterpret_cast<double*>(base + P.o_xs);
+  b.Vs = reinterpret_cast<double*>(base + P.o_vs);
+  b.KX = reinterpret_cast<double*>(base + P.o_kx);
+  b.KV = reinterpret_cast<double*>(base + P.o_kv);
+  const int* pre_pro = reinterpret_cast<const int*>(base + P.o_pre_pro);
+  const int* pre_pair = reinterpret_cast<const int*>(base + P.o_pre_pair);
+  const int* pre_epi = reinterpret_cast<const int*>(base + P.o_pre_epi);
+  for (int stage = 0; stage < 4; ++stage) {
+    b.stage = stage;
+    b.pos = stage == 0 ? X : b.Xs;
+    b.vel = stage == 0 ? V : b.Vs;
+    b.pre = pre_pro;
+    if (precision == PN_MIXED)
+      hipLaunchKernelGGL(k_prologue_batched<float>, dim3(P.pre_pro[n_sys]), dim3(kBlock), 0, st, b);
+    else
+      hipLaunchKernelGGL(k_prologue_batched<double>, dim3(P.pre_pro[n_sys]), dim3(kBlock), 0, st, b);
+    HIPCK(hipGetLastError());
+    b.pre = pre_pair;
+    if (precision == PN_MIXED)
+      hipLaunchKernelGGL(k_pair_batched<float>, dim3(P.pre_pair[n_sys]), dim3(kBlock), 0, st, b);
+    else
+      hipLaunchKernelGGL(k_pair_batched<double>, dim3(P.pre_pair[n_sys]), dim3(kBlock), 0, st, b);
+    HIPCK(hipGetLastError());
+    b.pre = pre_epi;
+    hipLaunchKernelGGL(k_epilogue_batched, dim3(P.pre_epi[n_sys]), dim3(kBlock), 0, st, b);
+    HIPCK(hipGetLastError());
+    hipLaunchKernelGGL(k_bh_final_batched, dim3(n_sys), dim3(kBlock), 0, st, b);
+    HIPCK(hipGetLastError());
+  }
+  return PN_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -511,6 +687,58 @@ int pn_accel(const double* pos, const double* vel, const double* mass, int64_t N
   if ((rc = enqueue_eval(s, P, sh, precision, o, st, &tm))) return rc;
   if ((rc = tm.collect((double)(N - 1) * (double)(N - 2)))) return rc;
   return finish(*d, P, st, flags & ~PN_TIMING);
+}
+
+int pn_accel_eih(const double* pos, const double* vel, const double* mass, int64_t N, double G,
+                 double c, double eps, int precision, double* acc_newton, double* phi,
+                 double* acc_1pn, void* stream, int flags) {
+  int rc = check_system(pos, mass, N, G, c, eps);
+  if (rc) return rc;
+  if (!dptr_ok(vel)) return PN_EINVAL;
+  if (precision != PN_FP64 && precision != PN_MIXED) return PN_EINVAL;
+  if ((acc_newton && !dptr_ok(acc_newton)) || (phi && !dptr_ok(phi)) ||
+      (acc_1pn && !dptr_ok(acc_1pn)))
+    return PN_EINVAL;
+  if (N >= ((int64_t)1 << 28)) return PN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState* d;
+  if ((rc = dev_state(&d))) return rc;
+  // both sweeps run over all N bodies: shapes and scratch sized for N "stars"
+  const Shape sh = pick_shape((int)N, precision);
+  const Layout L = layout_for(N + 1, sh, false);
+  if ((rc = ensure_scratch(*d, L.total))) return rc;
+  Ptrs P{d->base, L};
+  hipStream_t st = pick_stream(*d, stream);
+  if ((rc = reset_status(P, st))) return rc;
+  EihArgs e;
+  e.pos = pos;
+  e.vel = vel;
+  e.mass = mass;
+  e.N = (int)N;
+  e.G = G;
+  e.lam = lambda_of(c);
+  e.pk = P.at<void>(L.pk);
+  e.va = P.at<double>(L.ub);
+  e.part = P.at<double>(L.part);
+  e.nsplit = sh.nsplit;
+  e.acc_newton = acc_newton;
+  e.phi = phi;
+  e.acc_1pn = acc_1pn;
+  e.status = P.at<int>(L.status);
+  const int nb = (int)((N + kBlock - 1) / kBlock);
+  Sys all{pos, vel, mass, N + 1, G, c, eps};  // launch_pair sweeps Ns = N bodies
+  const bool mixed = precision == PN_MIXED;
+  if (mixed) hipLaunchKernelGGL(k_eih_packets<float>, dim3(nb), dim3(kBlock), 0, st, e);
+  else hipLaunchKernelGGL(k_eih_packets<double>, dim3(nb), dim3(kBlock), 0, st, e);
+  HIPCK(hipGetLastError());
+  if ((rc = launch_pair(all, P, sh, precision, MODE_P1, st))) return rc;
+  if (mixed) hipLaunchKernelGGL(k_eih_mid<float>, dim3(nb), dim3(kBlock), 0, st, e);
+  else hipLaunchKernelGGL(k_eih_mid<double>, dim3(nb), dim3(kBlock), 0, st, e);
+  HIPCK(hipGetLastError());
+  if ((rc = launch_pair(all, P, sh, precision, MODE_P2, st))) return rc;
+  hipLaunchKernelGGL(k_eih_final, dim3(nb), dim3(kBlock), 0, st, e);
+  HIPCK(hipGetLastError());
+  return finish(*d, P, st, flags);
 }
 
 int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, double c,
@@ -631,23 +859,85 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
                     int64_t nsteps, int precision, void* stream, int flags) {
   if (n_sys < 1 || !offsets || !G || !c || !eps) return PN_EINVAL;
   if (offsets[0] != 0) return PN_EINVAL;
+  if (!dptr_ok(vel) || !std::isfinite(dt) || nsteps < 0) return PN_EINVAL;
+  if (precision != PN_FP64 && precision != PN_MIXED) return PN_EINVAL;
   for (int b = 0; b < n_sys; ++b) {
     if (offsets[b + 1] - offsets[b] < 2) return PN_EINVAL;
     int rc = check_system(pos, mass, offsets[b + 1] - offsets[b], G[b], c[b], eps[b]);
     if (rc) return rc;
   }
-  for (int b = 0; b < n_sys; ++b) {
-    const int64_t o = offsets[b];
-    int rc = pn_step(pos + 3 * o, vel + 3 * o, mass + o, offsets[b + 1] - o, G[b], c[b], eps[b],
-                     dt, nsteps, precision, stream, flags | PN_ASYNC | PN_NOGRAPH);
-    if (rc) return rc;
-  }
-  if (flags & PN_ASYNC) return PN_OK;
+  if (offsets[n_sys] > ((int64_t)1 << 28)) return PN_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   DevState* d;
   int rc = dev_state(&d);
   if (rc) return rc;
-  HIPCK(hipStreamSynchronize(pick_stream(*d, stream)));
+  hipStream_t st = pick_stream(*d, stream);
+  const BatchPlan P = plan_batch(n_sys, offsets, G, c, eps);
+  if ((rc = ensure_batch_scratch(*d, P.total))) return rc;
+  char* base = d->bbase;
+  int* status = reinterpret_cast<int*>(base + P.o_status);
+  BatchKey key;
+  key.offsets.assign(offsets, offsets + n_sys + 1);
+  key.G.assign(G, G + n_sys);
+  key.c.assign(c, c + n_sys);
+  key.eps.assign(eps, eps + n_sys);
+  key.pos = pos;
+  key.vel = vel;
+  key.mass = mass;
+  key.dt = dt;
+  key.precision = precision;
+  key.base = base;
+  const bool graph = !(flags & PN_NOGRAPH);
+  const bool same = d->bgexec && key == d->bkey;
+  if (!same) {
+    // system descriptors, launch order and prefixes (host -> device, once per ensemble)
+    HIPCK(hipMemcpyAsync(base + P.o_sys, P.sys.data(), n_sys * sizeof(SysDev),
+                         hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(base + P.o_order, P.order.data(), n_sys * sizeof(int),
+                         hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(base + P.o_pre_pro, P.pre_pro.data(), (n_sys + 1) * sizeof(int),
+                         hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(base + P.o_pre_pair, P.pre_pair.data(), (n_sys + 1) * sizeof(int),
+                         hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(base + P.o_pre_epi, P.pre_epi.data(), (n_sys + 1) * sizeof(int),
+                         hipMemcpyHostToDevice, st));
+    HIPCK(hipStreamSynchronize(st));
+  }
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, st, status);
+  HIPCK(hipGetLastError());
+  if (nsteps > 0) {
+    if (!graph) {
+      for (int64_t k = 0; k < nsteps; ++k)
+        if ((rc = enqueue_batched_step(P, base, mass, pos, vel, dt, precision, st))) return rc;
+    } else {
+      if (!same) {
+        drop_batch_graph(*d);
+        HIPCK(hipStreamSynchronize(d->own));
+        HIPCK(hipStreamBeginCapture(d->own, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_batched_step(P, base, mass, pos, vel, dt, precision, d->own);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(d->own, &g);
+        if (rc) {
+          if (g) hipGraphDestroy(g);
+          return rc;
+        }
+        if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture", __LINE__);
+        d->bgraph = g;
+        HIPCK(hipGraphInstantiate(&d->bgexec, d->bgraph, nullptr, nullptr, 0));
+        d->bkey = key;
+      }
+      for (int64_t k = 0; k < nsteps; ++k) HIPCK(hipGraphLaunch(d->bgexec, st));
+    }
+  }
+  if (flags & PN_ASYNC) return PN_OK;
+  int hstatus = 0;
+  HIPCK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  if (hstatus & 2) {
+    snprintf(g_err, sizeof g_err, "mass of a massive object must be positive and finite");
+    return PN_EINVAL;
+  }
+  if (hstatus & 1) return PN_ENONFINITE;
   return PN_OK;
 }
 
@@ -697,6 +987,10 @@ int pn_release(void) {
     (void)hipSetDevice((int)dev);
     (void)hipDeviceSynchronize();
     drop_graph(d);
+    drop_batch_graph(d);
+    if (d.bbase) (void)hipFree(d.bbase);
+    d.bbase = nullptr;
+    d.bcap = 0;
     for (hipEvent_t e : d.ev) (void)hipEventDestroy(e);
     d.ev.clear();
     if (d.base) (void)hipFree(d.base);

@@ -145,9 +145,8 @@ struct ProArgs {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
-  __shared__ double lds[7 * kBlock];
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double* lds) {
+  const int k = blk * kBlock + threadIdx.x;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   if (k < a.Ns) {
     const int s = k + 1;
@@ -202,12 +201,18 @@ __global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
   }
   block_sum<7>(v, lds);
   if (threadIdx.x < 8) {
-    a.bpart[(size_t)blockIdx.x * 8 + threadIdx.x] = threadIdx.x < 7 ? lds[threadIdx.x * kBlock] : 0.0;
+    a.bpart[(size_t)blk * 8 + threadIdx.x] = threadIdx.x < 7 ? lds[threadIdx.x * kBlock] : 0.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk == 0 && threadIdx.x == 0) {
     const double M = a.mass[0];
     if (!(M > 0.0) || !isfinite(M)) atomicOr(a.status, 2);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
+  __shared__ double lds[7 * kBlock];
+  prologue_block<T>(a, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -345,14 +350,14 @@ __device__ __forceinline__ bool field_written(int f, int mode) {
 }
 
 template <typename T, int MODE, int IPT, int WS>
-__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
+__device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
   using Pk = typename PkOf<T>::type;
   constexpr int LANES = kBlock / WS;  // distinct i-lanes per workgroup
   constexpr int IB = LANES * IPT;     // i-bodies per workgroup
   const Pk* __restrict__ pk = static_cast<const Pk*>(a.pk);
   const int wave = WS > 1 ? wave_id() : 0;
   const int lane = WS > 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
-  const int ilo = blockIdx.x * IB;
+  const int ilo = ib * IB;
   const int ihi = min(a.Ns, ilo + IB);
   PairI<T, IPT> I;
 #pragma unroll
@@ -369,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
     I.kz[ii] = T(8.0 / 3.0) * (T)p.svz;
   }
   // j-range of this wavefront
-  int j0 = blockIdx.y * a.jchunk;
+  int j0 = sp * a.jchunk;
   int j1 = min(a.Ns, j0 + a.jchunk);
   if (WS > 1) {
     const int q = (j1 - j0 + WS - 1) / WS;
@@ -400,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
   }
 
   const size_t plane = (size_t)a.Ns;
-  double* out = a.part + (size_t)blockIdx.y * kNF * plane;
+  double* out = a.part + (size_t)sp * kNF * plane;
   if constexpr (WS == 1) {
 #pragma unroll
     for (int ii = 0; ii < IPT; ++ii) {
@@ -431,6 +436,11 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
       }
     }
   }
+}
+
+template <typename T, int MODE, int IPT, int WS>
+__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
+  pair_block<T, MODE, IPT, WS>(a, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -525,9 +535,8 @@ __device__ __forceinline__ bool epi_field_used(int f, const EpiArgs& a) {
   return !a.newton_only;
 }
 
-__global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
-  __shared__ double lds[7 * kBlock];
-  __shared__ double fsum[kNF * kEpiStars];
+__device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double* lds,
+                                               double* fsum) {
   double A0[3], V0, P[3];
   bh_quantities(a, lds, A0, V0, P);
   const double M = a.mass[0];
@@ -538,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   // split reduction: thread (g, l) sums fields g, g+4, g+8 of star l, in split order
   {
     const int g = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int k = blockIdx.x * kEpiStars + l;
+    const int k = blk * kEpiStars + l;
     if (k < a.Ns) {
       const size_t plane = (size_t)a.Ns;
       for (int f = g; f < kNF; f += 4) {
@@ -552,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   }
   __syncthreads();
 
-  const int k = blockIdx.x * kEpiStars + threadIdx.x;
+  const int k = blk * kEpiStars + threadIdx.x;
   double bh[3] = {0.0, 0.0, 0.0};
   if (threadIdx.x < kEpiStars && k < a.Ns) {
     const int i = k + 1;
@@ -636,11 +645,16 @@ __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   double bhs[3] = {bh[0], bh[1], bh[2]};
   block_sum<3>(bhs, lds);
   if (threadIdx.x < 4)
-    a.bhpart[(size_t)blockIdx.x * 4 + threadIdx.x] = threadIdx.x < 3 ? lds[threadIdx.x * kBlock] : 0.0;
+    a.bhpart[(size_t)blk * 4 + threadIdx.x] = threadIdx.x < 3 ? lds[threadIdx.x * kBlock] : 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_bh_final(EpiArgs a) {
+__global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   __shared__ double lds[7 * kBlock];
+  __shared__ double fsum[kNF * kEpiStars];
+  epilogue_block(a, blockIdx.x, lds, fsum);
+}
+
+__device__ __forceinline__ void bh_final_block(const EpiArgs& a, double* lds) {
   double A0[3], V0, P[3];
   bh_quantities(a, lds, A0, V0, P);
   double T[3] = {0.0, 0.0, 0.0};
@@ -672,6 +686,11 @@ __global__ __launch_bounds__(kBlock) void k_bh_final(EpiArgs a) {
       for (int c = 0; c < 3; ++c) rk4_update(a, (size_t)c, v0[c], at[c]);
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bh_final(EpiArgs a) {
+  __shared__ double lds[7 * kBlock];
+  bh_final_block(a, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -810,6 +829,266 @@ __global__ __launch_bounds__(kBlock) void k_diag_final(DiagEpiArgs a) {
       a.out8[5 + c] = a.lam * r[6 + c];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Unrestricted EIH equations for every pair (no massive-object truncation).
+// In EIH layout the full 1PN pair term of body a with partner b is
+//   (G m_b/R^2) n_ab [-v_a^2 - 2 v_b^2 + 4 v_a.v_b + 3/2 (n_ab.v_b)^2
+//                     + 4 V_a + V_b + 1/2 x_ab.a^N_b]
+//   + (G m_b/R^2) [n_ab.(4 v_a - 3 v_b)] (v_a - v_b) + 7/2 (G m_b/R) a^N_b,
+// the limited star-star term with u_b -> V_b (the full potential) and
+// -b_b -> a^N_b (the full Newtonian acceleration).  So it takes two sweeps
+// over all N bodies with the same pair kernel: pass 1 (MODE_P1) gives V and
+// a^N of every body; k_eih_mid writes them into the packets
+// (e = -2 v^2 + V, hb = a^N / 2); pass 2 (MODE_P2) sums the 1PN terms.
+// ---------------------------------------------------------------------------
+struct EihArgs {
+  const double* pos;
+  const double* vel;
+  const double* mass;
+  int N;
+  double G, lam;
+  void* pk;           // [N] packets of all bodies
+  double* va;         // [N][4]: V, a^N (3)
+  const double* part; // [nsplit][kNF][N]
+  int nsplit;
+  double* acc_newton; // outputs (any may be nullptr)
+  double* phi;
+  double* acc_1pn;
+  int* status;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_eih_packets(EihArgs a) {
+  using Pk = typename PkOf<T>::type;
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b < a.N) {
+    Pk p;
+    p.x = a.pos[3 * b];
+    p.y = a.pos[3 * b + 1];
+    p.z = a.pos[3 * b + 2];
+    p.gm = (T)(a.G * a.mass[b]);
+    p.svx = (T)(kSqrt32 * a.vel[3 * b]);
+    p.svy = (T)(kSqrt32 * a.vel[3 * b + 1]);
+    p.svz = (T)(kSqrt32 * a.vel[3 * b + 2]);
+    p.e = T(0);
+    p.hbx = T(0);
+    p.hby = T(0);
+    p.hbz = T(0);
+    if constexpr (sizeof(T) == 8) {
+      p.pad = 0.0;
+    } else {
+      p.pad0 = 0.f;
+      p.pad1 = 0.f;
+    }
+    static_cast<Pk*>(a.pk)[b] = p;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_eih_mid(EihArgs a) {
+  using Pk = typename PkOf<T>::type;
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b < a.N) {
+    const size_t plane = (size_t)a.N;
+    double U = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0;
+    for (int sp = 0; sp < a.nsplit; ++sp) {
+      const double* pp = a.part + (size_t)sp * kNF * plane + b;
+      U += pp[F_U * plane];
+      Gx += pp[F_G * plane];
+      Gy += pp[(F_G + 1) * plane];
+      Gz += pp[(F_G + 2) * plane];
+    }
+    const double aN[3] = {-Gx, -Gy, -Gz};
+    const double vx = a.vel[3 * b], vy = a.vel[3 * b + 1], vz = a.vel[3 * b + 2];
+    Pk& p = static_cast<Pk*>(a.pk)[b];
+    p.e = (T)(-2.0 * (vx * vx + vy * vy + vz * vz) + U);
+    p.hbx = (T)(0.5 * aN[0]);
+    p.hby = (T)(0.5 * aN[1]);
+    p.hbz = (T)(0.5 * aN[2]);
+    double* v4 = a.va + 4 * (size_t)b;
+    v4[0] = U;
+    v4[1] = aN[0];
+    v4[2] = aN[1];
+    v4[3] = aN[2];
+    if (a.phi) a.phi[b] = -U;
+    if (a.acc_newton) {
+      a.acc_newton[3 * b] = aN[0];
+      a.acc_newton[3 * b + 1] = aN[1];
+      a.acc_newton[3 * b + 2] = aN[2];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_eih_final(EihArgs a) {
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b < a.N) {
+    const size_t plane = (size_t)a.N;
+    double sum[kNF];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f) sum[f] = 0.0;
+    for (int sp = 0; sp < a.nsplit; ++sp) {
+      const double* pp = a.part + (size_t)sp * kNF * plane + b;
+#pragma unroll
+      for (int f = F_G; f < kNF; ++f) sum[f] += pp[f * plane];
+    }
+    sum[F_C2] *= kSqrt32;
+    const double* v4 = a.va + 4 * (size_t)b;
+    const double vx = a.vel[3 * b], vy = a.vel[3 * b + 1], vz = a.vel[3 * b + 2];
+    const double v[3] = {vx, vy, vz};
+    const double S0 = -(vx * vx + vy * vy + vz * vz) + 4.0 * v4[0];
+    double a1[3];
+    for (int c = 0; c < 3; ++c)
+      a1[c] = a.lam * (S0 * sum[F_G + c] + sum[F_Q + c] + sum[F_C2] * v[c] + 7.0 * sum[F_Q7 + c]);
+    if (a.acc_1pn) {
+      a.acc_1pn[3 * b] = a1[0];
+      a.acc_1pn[3 * b + 1] = a1[1];
+      a.acc_1pn[3 * b + 2] = a1[2];
+    }
+    bool bad = false;
+    for (int c = 0; c < 3; ++c) bad |= !isfinite(v4[1 + c] + a1[c]);
+    if (bad) atomicOr(a.status, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched ensemble: many independent systems in one launch per phase.
+// Every phase's workgroups are numbered system after system in the order
+// `order` (systems by decreasing cost, so the dispatcher, which starts
+// workgroups in index order, hands out the largest systems first);
+// `pre_*[r]` is the first workgroup of the r-th system in that order.  A
+// workgroup finds its system by binary search over pre_* (scalar loads) and
+// runs the same per-block code as the single-system kernels on that system's
+// slices of the concatenated arrays.
+// ---------------------------------------------------------------------------
+struct SysDev {
+  int64_t body0;  // first body (the massive object) in the concatenated body arrays
+  int64_t star0;  // first star in the concatenated star arrays (packets, u/b)
+  int64_t part0;  // first double of the system's pair partials
+  int Ns, nsplit, jchunk, iblocks;
+  int pro0, epi0;  // first row of the system's prologue / epilogue partials
+  int npro, nepi;  // number of those rows
+  double G, lam, eps2;
+};
+
+struct BatchArgs {
+  const SysDev* sys;
+  const int* order;
+  const int* pre;  // prefix of this phase's workgroups over `order`, n_sys+1 entries
+  int n_sys;
+  const double* pos;  // evaluation state, concatenated [sum N][3]
+  const double* vel;
+  const double* mass;
+  void* pk;  // packets of all stars
+  double* ub;
+  double* bpart;
+  double* part;
+  double* bhpart;
+  int* status;
+  int stage;
+  double dt;
+  double *X, *V, *Xs, *Vs, *KX, *KV;
+};
+
+// rank r of the system owning workgroup blk: pre[r] <= blk < pre[r+1]
+__device__ __forceinline__ int batch_rank(const int* pre, int n, int blk) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= blk) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ ProArgs batch_pro_args(const BatchArgs& b, const SysDev& S) {
+  using Pk = typename PkOf<T>::type;
+  ProArgs a;
+  a.pos = b.pos + 3 * S.body0;
+  a.vel = b.vel + 3 * S.body0;
+  a.mass = b.mass + S.body0;
+  a.Ns = S.Ns;
+  a.G = S.G;
+  a.eps2 = S.eps2;
+  a.pk = static_cast<Pk*>(b.pk) + S.star0;
+  a.ub = b.ub + 4 * S.star0;
+  a.bpart = b.bpart + 8 * (int64_t)S.pro0;
+  a.status = b.status;
+  return a;
+}
+
+__device__ __forceinline__ EpiArgs batch_epi_args(const BatchArgs& b, const SysDev& S) {
+  EpiArgs a;
+  const int64_t o3 = 3 * S.body0;
+  a.pos = b.pos + o3;
+  a.vel = b.vel + o3;
+  a.mass = b.mass + S.body0;
+  a.Ns = S.Ns;
+  a.G = S.G;
+  a.lam = S.lam;
+  a.eps2 = S.eps2;
+  a.ub = b.ub + 4 * S.star0;
+  a.bpart = b.bpart + 8 * (int64_t)S.pro0;
+  a.nbpro = S.npro;
+  a.part = b.part + S.part0;
+  a.nsplit = S.nsplit;
+  a.newton_only = 0;
+  a.phi_in = nullptr;
+  a.accN_in = nullptr;
+  a.acc_newton = nullptr;
+  a.phi = nullptr;
+  a.acc_1pn = nullptr;
+  a.bhpart = b.bhpart + 4 * (int64_t)S.epi0;
+  a.nbepi = S.nepi;
+  a.status = b.status;
+  a.stage = b.stage;
+  a.dt = b.dt;
+  a.X = b.X + o3;
+  a.V = b.V + o3;
+  a.Xs = b.Xs + o3;
+  a.Vs = b.Vs + o3;
+  a.KX = b.KX + o3;
+  a.KV = b.KV + o3;
+  return a;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prologue_batched(BatchArgs b) {
+  __shared__ double lds[7 * kBlock];
+  const int r = batch_rank(b.pre, b.n_sys, blockIdx.x);
+  const SysDev S = b.sys[b.order[r]];
+  prologue_block<T>(batch_pro_args<T>(b, S), blockIdx.x - b.pre[r], lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pair_batched(BatchArgs b) {
+  using Pk = typename PkOf<T>::type;
+  const int r = batch_rank(b.pre, b.n_sys, blockIdx.x);
+  const SysDev S = b.sys[b.order[r]];
+  const int local = blockIdx.x - b.pre[r];
+  PairArgs a;
+  a.pk = static_cast<const Pk*>(b.pk) + S.star0;
+  a.Ns = S.Ns;
+  a.jchunk = S.jchunk;
+  a.eps2 = S.eps2;
+  a.part = b.part + S.part0;
+  pair_block<T, MODE_FUSED, 1, 4>(a, local % S.iblocks, local / S.iblocks);
+}
+
+__global__ __launch_bounds__(kBlock) void k_epilogue_batched(BatchArgs b) {
+  __shared__ double lds[7 * kBlock];
+  __shared__ double fsum[kNF * kEpiStars];
+  const int r = batch_rank(b.pre, b.n_sys, blockIdx.x);
+  const SysDev S = b.sys[b.order[r]];
+  epilogue_block(batch_epi_args(b, S), blockIdx.x - b.pre[r], lds, fsum);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bh_final_batched(BatchArgs b) {
+  __shared__ double lds[7 * kBlock];
+  const SysDev S = b.sys[b.order[blockIdx.x]];
+  bh_final_block(batch_epi_args(b, S), lds);
 }
 
 }  // namespace pn

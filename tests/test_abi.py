@@ -30,7 +30,7 @@ def lib():
 
 def test_header_declares_the_entry_points():
     names = _declared()
-    for required in ("pn_potential_accel", "pn_correction", "pn_step", "pn_accel",
+    for required in ("pn_potential_accel", "pn_correction", "pn_step", "pn_accel", "pn_accel_eih",
                      "pn_diagnostics", "pn_step_batched", "pn_strerror", "pn_release",
                      "pn_last_timing"):
         assert required in names
@@ -79,6 +79,10 @@ def test_validation_without_device(lib):
     assert lib.pn_step(d, d, d, 16, 1.0, 30.0, 0.0, 1e-4, -1, 0, None, 0) == EINVAL
     assert lib.pn_step(d, d, d, 16, 1.0, 30.0, 0.0, 1e-4, 1, 7, None, 0) == EINVAL
     assert lib.pn_accel(d, d, d, 16, 1.0, 30.0, 0.0, 9, d, d, d, None, 0) == EINVAL
+    assert lib.pn_accel_eih(d, None, d, 16, 1.0, 30.0, 0.0, 0, d, d, d, None, 0) == EINVAL
+    assert lib.pn_accel_eih(d, d, d, 16, 1.0, 30.0, 0.0, 5, d, d, d, None, 0) == EINVAL
+    assert lib.pn_set_shape(0, 10, 5, 1, 4, 0) == EINVAL
+    assert lib.pn_set_shape(0, 2, 5, 3, 4, 0) == EINVAL
     assert lib.pn_diagnostics(d, d, d, 16, 1.0, 30.0, 0.0, None, None, 0) == EINVAL
     assert lib.pn_last_timing(None) == EINVAL
 

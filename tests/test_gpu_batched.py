@@ -1,0 +1,122 @@
+"""Batched ensembles (pn_step_batched): every system advances exactly as it
+would alone, whatever its neighbours in the batch.
+
+Tolerances: FP64 positions/velocities within 1e-13 of the same system run
+alone through pn_step (the two differ only in the summation order of the
+j-splits) and within 1e-12 of the oracle; mixed within 1e-8 of the oracle's
+positions.  Graph replay and direct launches agree bitwise; two runs agree
+bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_07986_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+G = 1.0
+
+
+@pytest.fixture(scope="module")
+def pn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_07986_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+# (N, M_bh, c, eps, seed): uneven sizes, ragged tails, a Newtonian member (c = inf)
+SYSTEMS = [(2, 0.1, 30.0, 1e-4, 1), (3, 0.05, 50.0, 1e-4, 2), (64, 0.1, 20.0, 1e-3, 3),
+           (300, 0.02, 80.0, 1e-4, 4), (1000, 0.1, math.inf, 1e-4, 5), (2049, 0.07, 25.0, 1e-4, 6),
+           (17, 0.1, 30.0, 0.0, 7)]
+
+
+def build_ensemble(systems):
+    ps, vs, ms, off = [], [], [], [0]
+    for N, M, c, eps, seed in systems:
+        p, v, m = inputs.plummer_bh(N, M, 500 + seed)
+        ps.append(p)
+        vs.append(v)
+        ms.append(m)
+        off.append(off[-1] + N)
+    return np.concatenate(ps), np.concatenate(vs), np.concatenate(ms), off
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def run_batched(pn, pos, vel, mass, off, systems, dt, steps, prec, flags=0):
+    P, V = dev(pos), dev(vel)
+    pn.pn_step_batched(off, [G] * len(systems), [s[2] for s in systems], [s[3] for s in systems],
+                       P, V, dev(mass), dt, steps, prec, flags=flags)
+    return P.cpu().numpy(), V.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_batched_equals_each_system_alone(pn, prec):
+    pos, vel, mass, off = build_ensemble(SYSTEMS)
+    dt, steps = 1e-4, 3
+    bp, bv = run_batched(pn, pos, vel, mass, off, SYSTEMS, dt, steps, prec)
+    for k, (N, M, c, eps, seed) in enumerate(SYSTEMS):
+        sl = slice(off[k], off[k + 1])
+        print(f"[system] {k} N={N} c={c} eps={eps}", flush=True)
+        P, V = dev(pos[sl]), dev(vel[sl])
+        pn.pn_step(P, V, dev(mass[sl]), G, c, eps, dt, steps, prec)
+        sp, sv = P.cpu().numpy(), V.cpu().numpy()
+        rp, rv = oracle.step(pos[sl], vel[sl], mass[sl], G, c, eps, dt, steps)
+        scale_p, scale_v = np.abs(rp).max(), np.abs(rv).max()
+        if prec == 0:
+            assert np.abs(bp[sl] - sp).max() <= 1e-13 * scale_p
+            assert np.abs(bv[sl] - sv).max() <= 1e-13 * scale_v
+            assert np.abs(bp[sl] - rp).max() <= 1e-12 * scale_p
+            assert np.abs(bv[sl] - rv).max() <= 1e-12 * scale_v
+        else:
+            assert np.abs(bp[sl] - rp).max() <= 1e-8 * scale_p
+            assert np.abs(bv[sl] - rv).max() <= 1e-6 * scale_v
+
+
+def test_batched_graph_equals_direct_and_is_deterministic(pn):
+    pos, vel, mass, off = build_ensemble(SYSTEMS)
+    a = run_batched(pn, pos, vel, mass, off, SYSTEMS, 1e-4, 4, 0)
+    b = run_batched(pn, pos, vel, mass, off, SYSTEMS, 1e-4, 4, 0, flags=pn.PN_NOGRAPH)
+    c = run_batched(pn, pos, vel, mass, off, SYSTEMS, 1e-4, 4, 0)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_batched_single_system_matches_pn_step_shape(pn):
+    """One system of N = 5000 in a batch of one, against pn_step with the
+    same shape (1 i per lane, 4 wavefronts, same split count): bitwise."""
+    N = 5000
+    pos, vel, mass = inputs.plummer_bh(N, 0.1, 77)
+    off = [0, N]
+    bp, bv = run_batched(pn, pos, vel, mass, off, [(N, 0.1, 30.0, 1e-4, 0)], 1e-4, 2, 0)
+    Ns = N - 1
+    iblocks = (Ns + 63) // 64
+    ns = max(1, min(min(16, -(-16384 // iblocks)), Ns // 128))  # the batched plan's rule
+    from paper_1801_07986_amd import _binding
+
+    pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
+    pn.pn_set_shape(0, N, N, 1, 4, ns)
+    try:
+        P, V = dev(pos), dev(vel)
+        pn.pn_step(P, V, dev(mass), G, 30.0, 1e-4, 1e-4, 2, 0)
+    finally:
+        pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
+        _binding.install_tuned_shapes()
+    assert np.array_equal(bp, P.cpu().numpy()) and np.array_equal(bv, V.cpu().numpy())
+
+
+def test_batched_invalid_mass(pn):
+    pos, vel, mass, off = build_ensemble(SYSTEMS[:3])
+    mass[off[1]] = -1.0  # massive object of the second system
+    with pytest.raises(pn.PNError) as e:
+        run_batched(pn, pos, vel, mass, off, SYSTEMS[:3], 1e-4, 1, 0)
+    assert e.value.code == pn.PN_EINVAL

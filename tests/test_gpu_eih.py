@@ -1,0 +1,67 @@
+"""Unrestricted EIH accelerations (pn_accel_eih) against the oracle.
+
+Tolerances as for the limited path (per-body relative error with the
+cancellation floor of test_gpu_parity): FP64 total <= 1e-12, 1PN part <= 1e-10;
+mixed total <= 1e-6, 1PN part <= 1e-4.  N = 2 with equal masses is checked
+against the textbook two-body 1PN relative acceleration.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_07986_amd import inputs
+from test_gpu_parity import body_rel, newton_scale
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+G = 1.0
+
+
+@pytest.fixture(scope="module")
+def pn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_07986_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def gpu_eih(pn, pos, vel, mass, c, eps, prec):
+    N = len(mass)
+    aN = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    phi = torch.empty(N, dtype=torch.float64, device="cuda:0")
+    a1 = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    pn.pn_accel_eih(dev(pos), dev(vel), dev(mass), G, c, eps, prec, aN, phi, a1)
+    return aN.cpu().numpy(), phi.cpu().numpy(), a1.cpu().numpy()
+
+
+@pytest.mark.parametrize("N", [2, 3, 64, 257, 1000, 2049])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_eih_parity(pn, N, prec):
+    print(f"[case] N={N} prec={prec}", flush=True)
+    pos, vel, mass = inputs.plummer_bh(N, 0.1, 900 + N)
+    vel[0] = [0.02, -0.01, 0.015]  # the massive object's own velocity enters here
+    c, eps = 30.0, 1e-4
+    aN, phi, a1 = gpu_eih(pn, pos, vel, mass, c, eps, prec)
+    rN, rphi, r1 = oracle.eih2(pos, vel, mass, G, c, eps)
+    s = newton_scale(pos, mass, eps)
+    tol, tol1 = (1e-12, 1e-10) if prec == 0 else (1e-6, 1e-4)
+    e, e1 = body_rel(aN + a1, rN + r1, s), body_rel(a1, r1, s, 1e-6)
+    print(f"N={N} prec={prec}: total {e.max():.3e} 1PN {e1.max():.3e}")
+    assert e.max() <= tol and e1.max() <= tol1
+    assert (np.abs(phi - rphi) / np.abs(rphi)).max() <= tol
+
+
+def test_eih_equal_mass_binary_is_textbook(pn):
+    pos = np.array([[0.3, -0.1, 0.2], [-0.4, 0.5, 0.1]])
+    vel = np.array([[0.1, 0.3, -0.05], [-0.1, -0.3, 0.05]])
+    mass = np.array([0.5, 0.5])
+    aN, phi, a1 = gpu_eih(pn, pos, vel, mass, 6.0, 0.0, 0)
+    n2, p2 = oracle.twobody(pos[1] - pos[0], vel[1] - vel[0], mass[1], mass[0], G, 6.0)
+    assert np.abs((a1[1] - a1[0]) - p2).max() <= 1e-13 * np.abs(p2).max()
+    assert np.abs((aN[1] - aN[0]) - n2).max() <= 1e-14 * np.abs(n2).max()

@@ -358,3 +358,45 @@ def test_p10_plummer_softening_closed_form(oracle_mod):
     assert np.abs(aN[0] - (G * m * x / R2**1.5)).max() < 1e-15 * G * m / R2
     assert abs(phi[1] + G * M / np.sqrt(R2)) < 1e-15 * G * M / np.sqrt(R2)
     assert abs(phi[0] + G * m / np.sqrt(R2)) < 1e-15 * G * m / np.sqrt(R2)
+
+
+# ---------------------------------------------------------------- unrestricted EIH
+def test_eih_two_body_exact_for_any_mass_ratio(oracle_mod):
+    """The unrestricted EIH equations for N = 2 are the textbook two-body 1PN
+    relative acceleration for every mass ratio (not only to O(m/M))."""
+    c = 7.0
+    for q in (1.0, 0.3, 1e-3):
+        M = 1.0
+        pos = np.array([[0.1, -0.2, 0.05], [1.1, 0.3, -0.4]])
+        vel = np.array([[0.0, 0.0, 0.0], [0.05, 0.45, 0.1]])
+        mass = np.array([M, q * M])
+        vel[0] = -q * vel[1]
+        for fn in (oracle_mod.eih, lambda *a: oracle_mod.eih2(*a)[::2]):
+            aN, a1 = fn(pos, vel, mass, G, c, 0.0)
+            n2, p2 = oracle_mod.twobody(pos[1] - pos[0], vel[1] - vel[0], mass[1], mass[0], G, c)
+            assert np.abs((a1[1] - a1[0]) - p2).max() < 1e-14 * np.abs(p2).max()
+            assert np.abs((aN[1] - aN[0]) - n2).max() < 1e-14 * np.abs(n2).max()
+
+
+def test_eih_potentials_once_equals_brute_force(oracle_mod):
+    """pnref_eih2 (V, a^N summed once) = pnref_eih (summed inside every pair)."""
+    pos, vel, mass = random_cluster(12, 21, M=0.3, m_star=0.05)
+    for eps in (0.0, 1e-2):
+        aN, a1 = oracle_mod.eih(pos, vel, mass, G, 9.0, eps)
+        bN, bphi, b1 = oracle_mod.eih2(pos, vel, mass, G, 9.0, eps)
+        assert _rel(bN, aN) < 1e-15 and _rel(b1, a1) < 1e-14
+
+
+def test_eih_reduces_to_limited_form_at_first_order(oracle_mod):
+    """Unrestricted minus limited is O(lm^2) in the stars' 1PN parts (the same
+    truncation statement as P2, through the O(N^2) form)."""
+    pos, vel, mass0 = random_cluster(5, 7, M=1.0, m_star=1.0)
+    res = []
+    for lm in (1e-2, 1e-3):
+        mass = mass0.copy()
+        mass[1:] *= lm
+        vel[0] = -(mass[1:, None] * vel[1:]).sum(0) / mass[0]
+        _, _, a1 = oracle_mod.accel(pos, vel, mass, G, 10.0, 0.0)
+        _, _, e1 = oracle_mod.eih2(pos, vel, mass, G, 10.0, 0.0)
+        res.append(np.abs(a1[1:] - e1[1:]).max())
+    assert 80 < res[0] / res[1] < 125
