@@ -52,6 +52,11 @@ def main() -> int:
     ap.add_argument("--workload", default="plummer_n16384_fp64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="skip the N=65536 comparison")
+    ap.add_argument("--table32", action="store_true",
+                    help="replicate the paper's Table 3.2 timing protocol instead")
+    ap.add_argument("--samples", type=int, default=10, help="samples per N for --table32")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB buffer 5 times (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -64,7 +69,12 @@ def main() -> int:
     import paper_1801_07986_amd as pn
     from paper_1801_07986_amd import inputs
 
+    if args.copy_calibration:
+        return copy_calibration(torch, args.copy_calibration)
     pn.load()
+    if args.table32:
+        print(json.dumps(table32(pn, torch, inputs, args.samples, not args.no_cpu)), flush=True)
+        return 0
     w = inputs.WORKLOADS[args.workload]
     N, c, eps, dt = w["N"], w["c"], w["eps"], w["dt"]
     prec = pn.PN_MIXED if w["precision"] == "mixed" else pn.PN_FP64
@@ -212,6 +222,82 @@ def ensemble(pn, torch, inputs, stream, steps=2):
         out[f"batched_over_sequential_{name}"] = ts / tb
         log(f"ensemble sequential {name}: {pairs / ts:.4e} pair/s")
     return out
+
+
+def copy_calibration(torch, mib):
+    """A plain device-to-device copy of known size, 5 times: the reference
+    for scaling the HBM counters (FETCH_SIZE, WRITE_SIZE) of a PMC run."""
+    n = mib * (1 << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "copies": 5}), flush=True)
+    return 0
+
+
+# The paper's Table 3.2 (Sec. 3.2): elapsed time of 32 RK4 steps plus the total
+# energy at the start and the end, mean and standard deviation of 10 samples,
+# on an NVIDIA Tesla K20c and on one core of an Intel Core i7-3770K.  Context
+# only (other hardware); the initial conditions of those runs are not stated.
+PAPER_TABLE32 = {100: (1.5392, 0.1299, 0.3479, 0.0043), 300: (1.9651, 0.1308, 3.0501, 0.0060),
+                 1000: (1.941, 0.1222, 33.652, 0.0881), 3000: (5.0517, 0.1284, 302.31, 0.10062),
+                 10000: (38.934, 0.0100, 3358.6, 2.1313), 30000: (339.956, 0.1391, 30188, 17.482)}
+
+
+def table32(pn, torch, inputs, samples, with_cpu):
+    """Table 3.2 protocol on this GPU: for each N, `samples` runs of (energy,
+    32 RK4 steps, energy) on the paper's test model (cold shell 1 < r < 10,
+    M = 100 m, c = G = 1, eps = 1e-3, dt = 2^-17), wall time from inputs on the
+    GPU to the final energy on the host.  CPU leg: the oracle (one thread, as
+    the paper's single core, and all threads) timed for one force evaluation
+    and one energy evaluation, scaled to 128 evaluations + 2 energies."""
+    import oracle
+
+    rows = []
+    dt = 2.0 ** -17
+    default_threads = oracle.max_threads()
+    for N, paper in PAPER_TABLE32.items():
+        pos0, vel0, mass0 = inputs.cold_sphere_bh(N - 1, seed=N)
+        times = []
+        for k in range(samples + 1):
+            pos = torch.from_numpy(pos0).cuda()
+            vel = torch.from_numpy(vel0).cuda()
+            mass = torch.from_numpy(mass0).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0 = pn.pn_diagnostics(pos, vel, mass, 1.0, 1.0, 1e-3)
+            pn.pn_step(pos, vel, mass, 1.0, 1.0, 1e-3, dt, 32, pn.PN_FP64)
+            e1 = pn.pn_diagnostics(pos, vel, mass, 1.0, 1.0, 1e-3)
+            t = time.perf_counter() - t0
+            if k > 0:  # the first run captures the step graph
+                times.append(t)
+        row = {"N": N, "gpu_mean_s": float(np.mean(times)), "gpu_std_s": float(np.std(times)),
+               "energy_rel_change": abs((e1[0] + e1[1]) - (e0[0] + e0[1])) / abs(e0[0] + e0[1]),
+               "paper_k20c_mean_s": paper[0], "paper_k20c_std_s": paper[1],
+               "paper_cpu1_mean_s": paper[2], "paper_cpu1_std_s": paper[3]}
+        if with_cpu:
+            for label, threads in (("cpu1", 1), ("cpu_all", default_threads)):
+                oracle.set_threads(threads)
+                nthr = oracle.max_threads()
+                t0 = time.perf_counter()
+                oracle.accel(pos0, vel0, mass0, 1.0, 1.0, 1e-3)
+                t_eval = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                oracle.diagnostics(pos0, vel0, mass0, 1.0, 1.0, 1e-3)
+                t_en = time.perf_counter() - t0
+                row[f"oracle_{label}_s"] = 128 * t_eval + 2 * t_en
+                row[f"oracle_{label}_threads"] = nthr
+                log(f"table32 N={N} oracle {label}: {row[f'oracle_{label}_s']:.2f} s "
+                    f"(extrapolated from one evaluation)")
+        rows.append(row)
+        log(f"table32 N={N}: GPU {row['gpu_mean_s'] * 1e3:.2f} +- {row['gpu_std_s'] * 1e3:.2f} ms "
+            f"(paper K20c {paper[0]} s, paper 1 core {paper[2]} s)")
+    return {"protocol": "Table 3.2: 32 RK4 steps + energy at start and end", "samples": samples,
+            "initial_conditions": "cold shell 1<r<10, M=100m, c=G=1, eps=1e-3, dt=2^-17",
+            "rows": rows}
 
 
 def cpu_baseline(pos, vel, mass, G, c, eps, budget_s=12.0):
