@@ -294,20 +294,21 @@ __device__ __forceinline__ void pair_one(const typename PkOf<T>::type& p, int j,
   }
 }
 
-// j loop with the next packet's scalar loads issued before the current
-// pair's arithmetic (software pipelining hides the load latency).
+// j loop over [j0, j1).
 template <typename T, int MODE, int IPT, bool MASK>
 __device__ __forceinline__ void pair_range(const typename PkOf<T>::type* __restrict__ pk, int j0,
                                            int j1, T eps2, const PairI<T, IPT>& I,
                                            PairAcc<T, IPT>& A) {
   using Pk = typename PkOf<T>::type;
-  if (j0 >= j1) return;
-  Pk cur = pk[j0];
-  for (int j = j0; j < j1; ++j) {
-    const Pk nxt = pk[min(j + 1, j1 - 1)];
-    pair_one<T, MODE, IPT, MASK>(cur, j, eps2, I, A);
-    cur = nxt;
+  int j = j0;
+  // two j per iteration: two independent dependency chains per wavefront
+  for (; j + 1 < j1; j += 2) {
+    const Pk p0 = pk[j];
+    const Pk p1 = pk[j + 1];
+    pair_one<T, MODE, IPT, MASK>(p0, j, eps2, I, A);
+    pair_one<T, MODE, IPT, MASK>(p1, j + 1, eps2, I, A);
   }
+  if (j < j1) pair_one<T, MODE, IPT, MASK>(pk[j], j, eps2, I, A);
 }
 
 template <typename T, int MODE, int IPT>
@@ -416,23 +417,33 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
       }
     }
   } else {
-    // fixed-order reduction over the WS wavefronts
-    __shared__ double red[WS * kNF * IPT * 64];
+    // fixed-order reduction over the WS wavefronts: waves 1..WS-1 park their
+    // sums in LDS, wave 0 adds them to its own in wave order and stores
+    // (LDS of WS-1 waves only, so it does not cap the occupancy)
+    __shared__ double red[(WS - 1) * kNF * IPT * 64];
+    if (wave > 0) {
 #pragma unroll
-    for (int f = 0; f < kNF; ++f)
+      for (int f = 0; f < kNF; ++f)
 #pragma unroll
-      for (int ii = 0; ii < IPT; ++ii) red[((wave * kNF + f) * IPT + ii) * 64 + lane] = acc[f][ii];
+        for (int ii = 0; ii < IPT; ++ii)
+          red[(((wave - 1) * kNF + f) * IPT + ii) * 64 + lane] = acc[f][ii];
+    }
     __syncthreads();
-    for (int v = threadIdx.x; v < kNF * IPT * 64; v += kBlock) {
-      const int f = v / (IPT * 64);
-      const int ii = (v / 64) % IPT;
-      const int l = v & 63;
-      const int idx = ilo + l + ii * 64;
-      if (idx < a.Ns && field_written(f, MODE)) {
-        double sum = 0.0;
+    if (wave == 0) {
 #pragma unroll
-        for (int w = 0; w < WS; ++w) sum += red[((w * kNF + f) * IPT + ii) * 64 + l];
-        out[f * plane + idx] = sum;
+      for (int ii = 0; ii < IPT; ++ii) {
+        const int idx = ilo + lane + ii * 64;
+        if (idx < a.Ns) {
+#pragma unroll
+          for (int f = 0; f < kNF; ++f) {
+            if (field_written(f, MODE)) {
+              double sum = acc[f][ii];
+#pragma unroll
+              for (int w = 1; w < WS; ++w) sum += red[(((w - 1) * kNF + f) * IPT + ii) * 64 + lane];
+              out[f * plane + idx] = sum;
+            }
+          }
+        }
       }
     }
   }
