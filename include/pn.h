@@ -138,6 +138,18 @@ int pn_diagnostics(const double* pos, const double* vel, const double* mass, int
                    double G, double c, double eps, double* out8, void* stream, int flags);
 
 /*
+ * Close-encounter diagnostics of the kind the paper's test-model figures
+ * follow (Sec. 4): distance of the star nearest to the massive object, the
+ * number of stars closer to it than r_close (e.g. a multiple of the
+ * Schwarzschild radius 2GM/c^2), and the nearest star-star pair.  Unsoftened
+ * distances; N >= 3.  out6 (HOST, 6 doubles): [min r_0s, its body index,
+ * count with r_0s < r_close, min r_ij, i, j] (i < j, body indices; ties go to
+ * the smallest indices).  Always synchronous.
+ */
+int pn_encounters(const double* pos, const double* mass, int64_t N, double r_close, double* out6,
+                  void* stream, int flags);
+
+/*
  * Many independent systems advanced together (each as pn_step would).
  * System b occupies bodies offsets[b] .. offsets[b+1]-1 of the concatenated
  * pos/vel/mass arrays, its massive object at offsets[b]; offsets (HOST, n_sys+1

@@ -13,7 +13,7 @@ from __future__ import annotations
 
 _BINDING_NAMES = (
     "pn_potential_accel", "pn_correction", "pn_accel", "pn_accel_eih", "pn_step", "pn_diagnostics",
-    "pn_step_batched", "pn_last_timing", "pn_release", "pn_strerror", "PNError",
+    "pn_step_batched", "pn_encounters", "pn_last_timing", "pn_release", "pn_strerror", "PNError",
     "PN_OK", "PN_EINVAL", "PN_ENONFINITE", "PN_EDEVICE", "PN_ENOMEM", "PN_FP64", "PN_MIXED",
     "PN_ASYNC", "PN_NOGRAPH", "PN_TIMING", "load", "LIB_PATH", "EXPORTS", "pn_set_shape",
     "install_tuned_shapes",

@@ -20,7 +20,7 @@ PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
 
 EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
            "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape",
-           "pn_accel_eih")
+           "pn_accel_eih", "pn_encounters")
 TUNED_PATH = os.path.join(HERE, "tuned_shapes.json")
 
 
@@ -46,6 +46,7 @@ def load():
         lib.pn_correction.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, vp, i32]
         lib.pn_accel.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
         lib.pn_accel_eih.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
+        lib.pn_encounters.argtypes = [vp, vp, i64, d, vp, vp, i32]
         lib.pn_step.argtypes = [vp, vp, vp, i64, d, d, d, d, i64, i32, vp, i32]
         lib.pn_diagnostics.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, i32]
         lib.pn_step_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, d, i64, i32,
@@ -150,6 +151,15 @@ def pn_diagnostics(pos, vel, mass, G, c, eps, stream=None, flags=0):
                                  ctypes.cast(out, ctypes.c_void_p), _stream(stream), flags),
            "pn_diagnostics")
     return list(out)
+
+
+def pn_encounters(pos, mass, r_close, stream=None, flags=0):
+    out = (ctypes.c_double * 6)()
+    _check(load().pn_encounters(_ptr(pos), _ptr(mass), _n(mass), r_close,
+                                ctypes.cast(out, ctypes.c_void_p), _stream(stream), flags),
+           "pn_encounters")
+    return {"min_r_bh": out[0], "nearest_to_bh": int(out[1]), "n_close_bh": int(out[2]),
+            "min_r_pair": out[3], "pair": (int(out[4]), int(out[5]))}
 
 
 def pn_step_batched(offsets, G, c, eps, pos, vel, mass, dt, nsteps, precision=PN_FP64,

@@ -854,6 +854,54 @@ int pn_diagnostics(const double* pos, const double* vel, const double* mass, int
   return finish(*d, P, st, 0);
 }
 
+int pn_encounters(const double* pos, const double* mass, int64_t N, double r_close, double* out6,
+                  void* stream, int flags) {
+  (void)flags;
+  if (!dptr_ok(pos) || !dptr_ok(mass) || N < 3 || N > ((int64_t)1 << 28) || !out6) return PN_EINVAL;
+  if (!(r_close >= 0.0) || std::isnan(r_close)) return PN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState* d;
+  int rc = dev_state(&d);
+  if (rc) return rc;
+  const int Ns = (int)(N - 1);
+  const int nb = (Ns + kBlock - 1) / kBlock;
+  Shape sh = pick_shape(Ns, PN_FP64);
+  const int nsplit = std::max(1, std::min(sh.nsplit * 4, std::max(1, Ns / 64)));
+  const int jchunk = (Ns + nsplit - 1) / nsplit;
+  const int ns = (Ns + jchunk - 1) / jchunk;
+  Shape s2 = sh;
+  s2.nsplit = std::max(sh.nsplit, ns);  // scratch for the larger split count
+  Layout L = layout_for(N, s2, false);
+  const size_t extra = align256((size_t)nb * 2 * sizeof(long long));
+  if ((rc = ensure_scratch(*d, L.total + extra))) return rc;
+  Ptrs P{d->base, L};
+  hipStream_t st = pick_stream(*d, stream);
+  Sys sys{pos, nullptr, mass, N, 1.0, 1.0, 0.0};
+  if ((rc = reset_status(P, st))) return rc;
+  if ((rc = launch_prologue(sys, P, PN_FP64, st))) return rc;  // packets hold the positions
+  EncArgs e;
+  e.pos = pos;
+  e.pk = P.at<PkF64>(L.pk);
+  e.Ns = Ns;
+  e.jchunk = jchunk;
+  e.r_close2 = r_close * r_close;
+  e.part = P.at<double>(L.part);
+  e.nsplit = ns;
+  e.bpart = P.at<double>(L.dpart);
+  e.bpair = reinterpret_cast<long long*>(d->base + L.total);
+  e.nb = nb;
+  e.out = P.at<double>(L.out8);
+  hipLaunchKernelGGL(k_enc_pair, dim3(nb, ns), dim3(kBlock), 0, st, e);
+  HIPCK(hipGetLastError());
+  hipLaunchKernelGGL(k_enc_star, dim3(nb), dim3(kBlock), 0, st, e);
+  HIPCK(hipGetLastError());
+  hipLaunchKernelGGL(k_enc_final, dim3(1), dim3(64), 0, st, e);
+  HIPCK(hipGetLastError());
+  HIPCK(hipMemcpyAsync(out6, P.at<double>(L.out8), 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  return PN_OK;
+}
+
 int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, const double* c,
                     const double* eps, double* pos, double* vel, const double* mass, double dt,
                     int64_t nsteps, int precision, void* stream, int flags) {

@@ -30,6 +30,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <climits>
 #include <stdint.h>
 
 namespace pn {
@@ -840,6 +841,144 @@ __global__ __launch_bounds__(kBlock) void k_diag_final(DiagEpiArgs a) {
       a.out8[5 + c] = a.lam * r[6 + c];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Close-encounter diagnostics (what the paper's test-model figures follow,
+// Sec. 4): the star nearest to the massive object, how many stars lie within
+// a given radius of it, and the nearest star-star pair.  Unsoftened
+// distances.  Minima carry the smaller index on ties, so results are exact
+// and order independent.
+// ---------------------------------------------------------------------------
+struct EncArgs {
+  const double* pos;
+  const PkF64* pk;  // star packets (positions)
+  int Ns, jchunk;
+  double r_close2;  // squared radius for the count
+  double* part;     // [gridDim.y][2][Ns]: per-star nearest r^2 and partner (as double)
+  int nsplit;
+  double* bpart;    // [blocks][4]: nearest BH r^2, its star, close count, nearest pair r^2
+  long long* bpair; // [blocks][2]: nearest pair (i, j)
+  int nb;
+  double* out;      // [6] final
+};
+
+__device__ __forceinline__ bool enc_less(double r2a, long long ia, double r2b, long long ib) {
+  return r2a < r2b || (r2a == r2b && ia < ib);
+}
+
+__global__ __launch_bounds__(kBlock) void k_enc_pair(EncArgs a) {
+  const PkF64* __restrict__ pk = a.pk;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const PkF64& pi = pk[min(i, a.Ns - 1)];
+  const double xi = pi.x, yi = pi.y, zi = pi.z;
+  const int j0 = blockIdx.y * a.jchunk, j1 = min(a.Ns, j0 + a.jchunk);
+  double best = INFINITY;
+  int bj = -1;
+  for (int j = j0; j < j1; ++j) {
+    const PkF64& p = pk[j];
+    const double dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (j != i && r2 < best) {  // strict: the first (smallest) j wins ties
+      best = r2;
+      bj = j;
+    }
+  }
+  if (i < a.Ns) {
+    double* out = a.part + (size_t)blockIdx.y * 2 * a.Ns + i;
+    out[0] = best;
+    out[a.Ns] = (double)bj;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_enc_star(EncArgs a) {
+  __shared__ double s_r2[kBlock], s_pr2[kBlock], s_cnt[kBlock];
+  __shared__ long long s_i[kBlock], s_pi[kBlock], s_pj[kBlock];
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  double r2 = INFINITY, pr2 = INFINITY, cnt = 0.0;
+  long long idx = LLONG_MAX, pi_ = LLONG_MAX, pj_ = LLONG_MAX;
+  if (k < a.Ns) {
+    const double dx = a.pos[3 * (k + 1)] - a.pos[0], dy = a.pos[3 * (k + 1) + 1] - a.pos[1],
+                 dz = a.pos[3 * (k + 1) + 2] - a.pos[2];
+    r2 = dx * dx + dy * dy + dz * dz;
+    idx = k + 1;
+    cnt = r2 < a.r_close2 ? 1.0 : 0.0;
+    for (int sp = 0; sp < a.nsplit; ++sp) {
+      const double* p = a.part + (size_t)sp * 2 * a.Ns + k;
+      const long long j = (long long)p[a.Ns];
+      if (j >= 0 && enc_less(p[0], j, pr2, pj_)) {
+        pr2 = p[0];
+        pj_ = j;
+      }
+    }
+    if (pj_ != LLONG_MAX) {  // the pair as (smaller, larger) body index
+      const long long bi = k + 1, bj = pj_ + 1;
+      pi_ = bi < bj ? bi : bj;
+      pj_ = bi < bj ? bj : bi;
+    }
+  }
+  s_r2[threadIdx.x] = r2;
+  s_i[threadIdx.x] = idx;
+  s_cnt[threadIdx.x] = cnt;
+  s_pr2[threadIdx.x] = pr2;
+  s_pi[threadIdx.x] = pi_;
+  s_pj[threadIdx.x] = pj_;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    const int t = threadIdx.x;
+    if (t < s) {
+      if (enc_less(s_r2[t + s], s_i[t + s], s_r2[t], s_i[t])) {
+        s_r2[t] = s_r2[t + s];
+        s_i[t] = s_i[t + s];
+      }
+      s_cnt[t] += s_cnt[t + s];
+      const bool take = s_pr2[t + s] < s_pr2[t] ||
+                        (s_pr2[t + s] == s_pr2[t] &&
+                         (s_pi[t + s] < s_pi[t] || (s_pi[t + s] == s_pi[t] && s_pj[t + s] < s_pj[t])));
+      if (take) {
+        s_pr2[t] = s_pr2[t + s];
+        s_pi[t] = s_pi[t + s];
+        s_pj[t] = s_pj[t + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* b = a.bpart + 4 * (size_t)blockIdx.x;
+    b[0] = s_r2[0];
+    b[1] = (double)s_i[0];
+    b[2] = s_cnt[0];
+    b[3] = s_pr2[0];
+    a.bpair[2 * (size_t)blockIdx.x] = s_pi[0];
+    a.bpair[2 * (size_t)blockIdx.x + 1] = s_pj[0];
+  }
+}
+
+__global__ void k_enc_final(EncArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double r2 = INFINITY, cnt = 0.0, pr2 = INFINITY;
+  long long idx = LLONG_MAX, pi_ = LLONG_MAX, pj_ = LLONG_MAX;
+  for (int b = 0; b < a.nb; ++b) {
+    const double* p = a.bpart + 4 * (size_t)b;
+    const long long bi = (long long)p[1];
+    if (enc_less(p[0], bi, r2, idx)) {
+      r2 = p[0];
+      idx = bi;
+    }
+    cnt += p[2];
+    const long long qi = a.bpair[2 * (size_t)b], qj = a.bpair[2 * (size_t)b + 1];
+    if (p[3] < pr2 || (p[3] == pr2 && (qi < pi_ || (qi == pi_ && qj < pj_)))) {
+      pr2 = p[3];
+      pi_ = qi;
+      pj_ = qj;
+    }
+  }
+  a.out[0] = sqrt(r2);
+  a.out[1] = (double)idx;
+  a.out[2] = cnt;
+  a.out[3] = sqrt(pr2);
+  a.out[4] = (double)pi_;
+  a.out[5] = (double)pj_;
 }
 
 // ---------------------------------------------------------------------------

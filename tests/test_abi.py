@@ -84,6 +84,8 @@ def test_validation_without_device(lib):
     assert lib.pn_set_shape(0, 10, 5, 1, 4, 0) == EINVAL
     assert lib.pn_set_shape(0, 2, 5, 3, 4, 0) == EINVAL
     assert lib.pn_diagnostics(d, d, d, 16, 1.0, 30.0, 0.0, None, None, 0) == EINVAL
+    assert lib.pn_encounters(d, d, 2, 0.1, d, None, 0) == EINVAL
+    assert lib.pn_encounters(d, d, 16, -0.1, d, None, 0) == EINVAL
     assert lib.pn_last_timing(None) == EINVAL
 
 

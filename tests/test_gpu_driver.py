@@ -1,0 +1,69 @@
+"""Close-encounter diagnostics and the simulation driver.
+
+pn_encounters against a brute-force numpy search (minimum distances to
+rounding, indices and counts exactly); the driver's checkpoint/resume is
+bitwise identical to an uninterrupted run.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from paper_1801_07986_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_07986_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+@pytest.mark.parametrize("N", [3, 100, 3001])
+def test_encounters_brute_force(pn, N):
+    pos, vel, mass = inputs.plummer_bh(N, 0.1, 40 + N)
+    r_close = 0.3
+    got = pn.pn_encounters(dev(pos), dev(mass), r_close)
+    rb = np.linalg.norm(pos[1:] - pos[0], axis=1)
+    k = int(np.argmin(rb))
+    assert got["nearest_to_bh"] == k + 1
+    assert abs(got["min_r_bh"] - rb[k]) <= 1e-15 * rb[k]
+    assert got["n_close_bh"] == int((rb < r_close).sum())
+    s = pos[1:]
+    d = np.sqrt(((s[:, None, :] - s[None, :, :]) ** 2).sum(-1))
+    d[np.arange(N - 1), np.arange(N - 1)] = np.inf
+    i, j = np.unravel_index(np.argmin(d), d.shape)
+    assert tuple(sorted((i + 1, j + 1))) == got["pair"]
+    assert abs(got["min_r_pair"] - d[i, j]) <= 1e-15 * d[i, j]
+
+
+def test_driver_resume_is_bitwise(pn, tmp_path):
+    from paper_1801_07986_amd import simulate
+
+    pos, vel, mass = inputs.cold_sphere_bh(400, seed=3)
+    kw = dict(G=1.0, c=1.0, eps=1e-3, dt=2.0 ** -12, every=2.0 ** -9, precision="fp64")
+    P, V, M = dev(pos), dev(vel), dev(mass)
+    simulate.run(P, V, M, t_end=2.0 ** -7, out_path=str(tmp_path / "a.jsonl"), **kw)
+    ck = str(tmp_path / "ck.npz")
+    P2, V2 = dev(pos), dev(vel)
+    simulate.run(P2, V2, M, t_end=2.0 ** -8, out_path=str(tmp_path / "b.jsonl"), checkpoint=ck,
+                 **kw)
+    p3, v3, m3, meta = simulate.load_checkpoint(ck)
+    P3, V3 = dev(p3), dev(v3)
+    simulate.run(P3, V3, dev(m3), t_end=2.0 ** -7, out_path=str(tmp_path / "b.jsonl"),
+                 t0=meta["t"], step0=meta["step"], E_ref=meta["E_ref"], **kw)
+    assert np.array_equal(P.cpu().numpy(), P3.cpu().numpy())
+    assert np.array_equal(V.cpu().numpy(), V3.cpu().numpy())
+    a = [json.loads(x) for x in open(tmp_path / "a.jsonl")]
+    b = [json.loads(x) for x in open(tmp_path / "b.jsonl")]
+    assert a[-1]["E"] == b[-1]["E"] and a[-1]["t"] == b[-1]["t"]
