@@ -63,6 +63,10 @@ def _load():
                            ctypes.c_double, ctypes.c_double, _i64],
             "pnref_diagnostics": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, _dp],
+            "pnref_jerk": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_double, _dp, _dp],
+            "pnref_hermite": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_double, _i64, ctypes.c_double],
         }
         for name, argtypes in sig.items():
             fn = getattr(lib, name)
@@ -175,6 +179,25 @@ def step(pos, vel, mass, G, c, eps, dt, nsteps):
     pos, vel, mass = _arr(pos, (N, 3)).copy(), _arr(vel, (N, 3)).copy(), _arr(mass, (N,))
     _check(_load().pnref_step(_p(pos), _p(vel), _p(mass), N, G, c, eps, dt, nsteps),
            "pnref_step")
+    return pos, vel
+
+
+def jerk(pos, vel, mass, G, c, eps, h=1e-4):
+    """(acceleration, jerk along the motion) by Richardson central differences."""
+    N = len(mass)
+    pos, vel, mass = _arr(pos, (N, 3)), _arr(vel, (N, 3)), _arr(mass, (N,))
+    a, j = np.empty((N, 3)), np.empty((N, 3))
+    _check(_load().pnref_jerk(_p(pos), _p(vel), _p(mass), N, G, c, eps, h, _p(a), _p(j)),
+           "pnref_jerk")
+    return a, j
+
+
+def hermite(pos, vel, mass, G, c, eps, dt, nsteps, h=1e-4):
+    """Advance copies of (pos, vel) by nsteps fixed Hermite steps; returns them."""
+    N = len(mass)
+    pos, vel, mass = _arr(pos, (N, 3)).copy(), _arr(vel, (N, 3)).copy(), _arr(mass, (N,))
+    _check(_load().pnref_hermite(_p(pos), _p(vel), _p(mass), N, G, c, eps, dt, nsteps, h),
+           "pnref_hermite")
     return pos, vel
 
 

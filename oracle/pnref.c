@@ -722,6 +722,103 @@ int pnref_step(double *pos, double *vel, const double *mass, idx_t N, double G, 
 }
 
 /* ------------------------------------------------------------------ */
+/* Jerk (time derivative of the acceleration along the motion, needed by */
+/* the Hermite scheme the paper proposes in Sec. 5 / Appendix A):        */
+/*   jerk = d/dh a(x + h v, v + h a) at h = 0,                          */
+/* the derivative of the limited-1PN acceleration in the direction of   */
+/* the flow, by Richardson-extrapolated central differences:            */
+/*   [8 (a(h) - a(-h)) - (a(2h) - a(-2h))] / (12 h),  error O(h^4).     */
+/* acc_out receives a itself.                                            */
+/* ------------------------------------------------------------------ */
+int pnref_jerk(const double *pos, const double *vel, const double *mass, idx_t N, double G,
+               double c, double eps, double h, double *acc_out, double *jerk) {
+  int rc = check_common(pos, mass, N, G, eps);
+  if (rc) return rc;
+  if (check_c(c) || !vel || !acc_out || !jerk || !(h > 0.0)) return PNREF_EINVAL;
+  const idx_t n3 = 3 * N;
+  double *buf = (double *)malloc(sizeof(double) * (size_t)n3 * 6 + sizeof(double) * N);
+  if (!buf) return PNREF_ENOMEM;
+  double *xs = buf, *vs = xs + n3, *aN = vs + n3, *a1 = aN + n3, *ap = a1 + n3,
+         *am = ap + n3, *ph = am + n3;
+  if ((rc = pnref_accel(pos, vel, mass, N, G, c, eps, aN, ph, a1))) goto done;
+  for (idx_t t = 0; t < n3; ++t) acc_out[t] = aN[t] + a1[t];
+  for (idx_t t = 0; t < n3; ++t) jerk[t] = 0.0;
+  for (int k = 1; k <= 2; ++k) {
+    const double w = (k == 1) ? 8.0 : -1.0;
+    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+      const double hh = sgn * k * h;
+      for (idx_t t = 0; t < n3; ++t) {
+        xs[t] = pos[t] + hh * vel[t];
+        vs[t] = vel[t] + hh * acc_out[t];
+      }
+      if ((rc = pnref_accel(xs, vs, mass, N, G, c, eps, aN, ph, a1))) goto done;
+      double *dst = (sgn > 0) ? ap : am;
+      for (idx_t t = 0; t < n3; ++t) dst[t] = aN[t] + a1[t];
+    }
+    for (idx_t t = 0; t < n3; ++t) jerk[t] += w * (ap[t] - am[t]);
+  }
+  for (idx_t t = 0; t < n3; ++t) jerk[t] /= 12.0 * h;
+done:
+  free(buf);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Fourth-order Hermite scheme with a fixed step (predict, evaluate,    */
+/* correct), the scheme the paper names as the remedy for close          */
+/* encounters (Sec. 4-5):                                               */
+/*   x_p = x + v dt + a dt^2/2 + j dt^3/6 + s dt^4/24 + k dt^5/120       */
+/*   v_p = v + a dt + j dt^2/2 + s dt^3/6 + k dt^4/24                    */
+/*   (a_p, j_p) at (x_p, v_p)                                           */
+/*   v' = v + (a + a_p) dt/2 + (j - j_p) dt^2/12                         */
+/*   x' = x + (v + v') dt/2 + (a - a_p) dt^2/12                          */
+/* s, k (snap, crackle) come from the step's Hermite interpolation of   */
+/* a:  s_0 = (-6 (a - a_p) - dt (4 j + 2 j_p)) / dt^2,                   */
+/*     k = (12 (a - a_p) + 6 dt (j + j_p)) / dt^3,  s <- s_0 + k dt,     */
+/* and are zero before the first step.  The velocity-dependent 1PN force */
+/* makes the predicted velocity matter: with the plain predictor         */
+/* (a and j only) its O(dt^3) error would leave the scheme third order.  */
+/* Jerks from pnref_jerk with difference step h.                         */
+/* ------------------------------------------------------------------ */
+int pnref_hermite(double *pos, double *vel, const double *mass, idx_t N, double G, double c,
+                  double eps, double dt, idx_t nsteps, double h) {
+  int rc = check_common(pos, mass, N, G, eps);
+  if (rc) return rc;
+  if (check_c(c) || !vel || !isfinite(dt) || !(dt > 0.0) || nsteps < 0 || !(h > 0.0))
+    return PNREF_EINVAL;
+  const idx_t n3 = 3 * N;
+  double *buf = (double *)malloc(sizeof(double) * (size_t)n3 * 8);
+  if (!buf) return PNREF_ENOMEM;
+  double *a = buf, *j = a + n3, *sn = j + n3, *cr = sn + n3, *xp = cr + n3, *vp = xp + n3,
+         *ap = vp + n3, *jp = ap + n3;
+  const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
+  if ((rc = pnref_jerk(pos, vel, mass, N, G, c, eps, h, a, j))) goto done;
+  for (idx_t t = 0; t < n3; ++t) sn[t] = cr[t] = 0.0;
+  for (idx_t step = 0; step < nsteps; ++step) {
+    for (idx_t t = 0; t < n3; ++t) {
+      xp[t] = pos[t] + dt * vel[t] + dt2 / 2.0 * a[t] + dt3 / 6.0 * j[t] + dt4 / 24.0 * sn[t] +
+              dt5 / 120.0 * cr[t];
+      vp[t] = vel[t] + dt * a[t] + dt2 / 2.0 * j[t] + dt3 / 6.0 * sn[t] + dt4 / 24.0 * cr[t];
+    }
+    if ((rc = pnref_jerk(xp, vp, mass, N, G, c, eps, h, ap, jp))) break;
+    for (idx_t t = 0; t < n3; ++t) {
+      double vn = vel[t] + dt / 2.0 * (a[t] + ap[t]) + dt2 / 12.0 * (j[t] - jp[t]);
+      pos[t] = pos[t] + dt / 2.0 * (vel[t] + vn) + dt2 / 12.0 * (a[t] - ap[t]);
+      vel[t] = vn;
+      double s0 = (-6.0 * (a[t] - ap[t]) - dt * (4.0 * j[t] + 2.0 * jp[t])) / dt2;
+      double k = (12.0 * (a[t] - ap[t]) + 6.0 * dt * (j[t] + jp[t])) / dt3;
+      sn[t] = s0 + k * dt;
+      cr[t] = k;
+      a[t] = ap[t];
+      j[t] = jp[t];
+    }
+  }
+done:
+  free(buf);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Conserved quantities, Eqs. (7) and (8), by direct summation as       */
 /* printed.  Double sums over i, j run over ordered star pairs with     */
 /* i != j wherever r_ij appears; the last term of Eq. (7),             */

@@ -400,3 +400,46 @@ def test_eih_reduces_to_limited_form_at_first_order(oracle_mod):
         _, _, e1 = oracle_mod.eih2(pos, vel, mass, G, 10.0, 0.0)
         res.append(np.abs(a1[1:] - e1[1:]).max())
     assert 80 < res[0] / res[1] < 125
+
+
+# ---------------------------------------------------------------- Hermite (jerk)
+def test_jerk_newtonian_closed_form(oracle_mod):
+    """c = inf: the jerk of a body in a two-body orbit is the textbook
+    -G M [v/r^3 - 3 (r.v) r / r^5] (relative coordinates)."""
+    M, m = 1.0, 1e-3
+    x, v = np.array([0.7, -0.2, 0.3]), np.array([0.1, 0.9, -0.2])
+    pos, vel, mass = np.array([[0, 0, 0], x]), np.array([[0, 0, 0], v]), np.array([M, m])
+    a, j = oracle_mod.jerk(pos, vel, mass, G, np.inf, 0.0, h=3e-4)
+    r = np.linalg.norm(x)
+    jex = -G * M * (v / r**3 - 3 * (x @ v) * x / r**5)
+    assert np.abs(j[1] - jex).max() < 1e-11 * np.abs(jex).max()
+
+
+def test_jerk_converges_as_h4(oracle_mod):
+    """The 1PN jerk from differences of the oracle's acceleration along the
+    motion converges as h^4 (Richardson-extrapolated central differences)."""
+    pos, vel, mass = _circ_cluster(5, ns=4, mstar=1e-2)
+    _, jref = oracle_mod.jerk(pos, vel, mass, G, 8.0, 1e-3, h=4e-4)
+    errs = [np.abs(oracle_mod.jerk(pos, vel, mass, G, 8.0, 1e-3, h=h)[1] - jref).max()
+            for h in (8e-3, 4e-3)]
+    assert 10 < errs[0] / errs[1] < 22
+
+
+def test_hermite_fourth_order_and_precession(oracle_mod):
+    """The Hermite scheme integrates the same equations as RK4 to fourth
+    order: halving dt cuts the one-orbit error ~16x, and the results of both
+    integrators agree."""
+    a_, M, e = 1.0, 1.0, 0.5
+    c = np.sqrt(G * M / (1e-3 * a_))
+    rp, vp = a_ * (1 - e), np.sqrt(G * M * (1 + e) / (a_ * (1 - e)))
+    pos = np.array([[0, 0, 0], [rp, 0, 0]], float)
+    vel = np.array([[0, 0, 0], [0, vp, 0]], float)
+    mass = np.array([M, 1e-12])
+    T = 2 * np.pi
+    ref, _ = oracle_mod.step(pos, vel, mass, G, c, 0.0, T / 8000, 8000)
+    errs = []
+    for n in (500, 1000):
+        p, _ = oracle_mod.hermite(pos, vel, mass, G, c, 0.0, T / n, n, h=2e-5)
+        errs.append(np.abs(p[1] - ref[1]).max())
+    assert 12 < errs[0] / errs[1] < 20
+    assert errs[1] < 1e-6
