@@ -146,6 +146,8 @@ def main() -> int:
 
     if not args.no_secondary:
         result["secondary"] = secondary(pn, torch, inputs, stream)
+        result["hermite"] = hermite(pn, torch, inputs, stream, args.workload,
+                                    result["ms_per_step"])
         result["ensemble"] = ensemble(pn, torch, inputs, stream)
 
     if not args.no_cpu:
@@ -175,6 +177,26 @@ def secondary(pn, torch, inputs, stream):
         log(f"secondary N={N} {name}: {out[name + '_pair_per_s']:.4e} pair/s")
     out["mixed_over_fp64"] = out["mixed_pair_per_s"] / out["fp64_pair_per_s"]
     return out
+
+
+def hermite(pn, torch, inputs, stream, workload, rk4_ms, steps=50):
+    """The same workload advanced by the fourth-order Hermite scheme (FP64):
+    per step one FP64 evaluation and one dual-number jerk sweep."""
+    w = inputs.WORKLOADS[workload]
+    N = w["N"]
+    pos0, vel0, mass0 = inputs.plummer_bh(N, w["M_bh"], w["seed"])
+    pos = torch.from_numpy(pos0).cuda()
+    vel = torch.from_numpy(vel0).cuda()
+    mass = torch.from_numpy(mass0).cuda()
+    pn.pn_step_hermite(pos, vel, mass, 1.0, w["c"], w["eps"], w["dt"], 2, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pn.pn_step_hermite(pos, vel, mass, 1.0, w["c"], w["eps"], w["dt"], steps, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    log(f"hermite N={N}: {ms:.4f} ms/step (RK4 {rk4_ms:.4f} ms/step)")
+    return {"workload": workload, "N": N, "steps": steps, "ms_per_step": ms,
+            "rk4_ms_per_step": rk4_ms, "hermite_over_rk4_time": ms / rk4_ms}
 
 
 def ensemble(pn, torch, inputs, stream, steps=2):

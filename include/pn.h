@@ -128,6 +128,38 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
             double eps, double dt, int64_t nsteps, int precision, void* stream, int flags);
 
 /*
+ * Total acceleration a = a^N + a^1PN of all N bodies and its time derivative
+ * along the motion, the jerk j = (d/dt) a(x(t), v(t)) = (v . grad_x) a +
+ * (a . grad_v) a, which the fourth-order Hermite scheme the paper proposes
+ * for close encounters (Sec. 4, Sec. 5, Appendix) needs.  Computed exactly
+ * (to rounding) in FP64 by forward-mode differentiation of the evaluation:
+ * one FP64 evaluation gives a, then the same sweep on dual numbers (value,
+ * derivative) with positions (x, v) and velocities (v, a).  Outputs acc, jerk:
+ * [N][3] device arrays, both required; vel[0] enters through the 1PN terms'
+ * derivatives only as pn_accel uses it.  FP64 only.
+ */
+int pn_jerk(const double* pos, const double* vel, const double* mass, int64_t N, double G,
+            double c, double eps, double* acc, double* jerk, void* stream, int flags);
+
+/*
+ * Advance (pos, vel) of all N bodies by nsteps fixed steps of the
+ * fourth-order Hermite scheme (Sec. 4-5, Appendix), FP64:
+ *   predict  x_p = x + v dt + a dt^2/2 + j dt^3/6 + s dt^4/24 + k dt^5/120,
+ *            v_p = v + a dt + j dt^2/2 + s dt^3/6 + k dt^4/24,
+ *   evaluate (a_p, j_p) at (x_p, v_p) as pn_jerk does,
+ *   correct  v' = v + (a + a_p) dt/2 + (j - j_p) dt^2/12,
+ *            x' = x + (v + v') dt/2 + (a - a_p) dt^2/12,
+ * with snap s and crackle k from the step's Hermite interpolant of a
+ * (k = (12 (a - a_p) + 6 dt (j + j_p))/dt^3, s = (-6 (a - a_p) -
+ * dt (4 j + 2 j_p))/dt^2 + k dt), both zero before the first step.  Each call
+ * starts afresh from (a, j) at the given state; one call of n1 + n2 steps
+ * therefore differs (at O(dt^5)) from two calls of n1 and n2.  Two sweeps per
+ * step (the FP64 one and the dual one).  dt > 0; nsteps = 0 is a no-op.
+ */
+int pn_step_hermite(double* pos, double* vel, const double* mass, int64_t N, double G, double c,
+                    double eps, double dt, int64_t nsteps, void* stream, int flags);
+
+/*
  * Conserved quantities of Sec. 2: 1PN total energy (Eq. (7)) and momentum
  * (Eq. (8)), by the sum conventions of those equations (ordered star pairs
  * i != j where r_ij appears; the last sum of Eq. (7) includes i = j).

@@ -20,7 +20,7 @@ PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
 
 EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
            "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape",
-           "pn_accel_eih", "pn_encounters")
+           "pn_accel_eih", "pn_encounters", "pn_jerk", "pn_step_hermite")
 TUNED_PATH = os.path.join(HERE, "tuned_shapes.json")
 
 
@@ -48,6 +48,8 @@ def load():
         lib.pn_accel_eih.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
         lib.pn_encounters.argtypes = [vp, vp, i64, d, vp, vp, i32]
         lib.pn_step.argtypes = [vp, vp, vp, i64, d, d, d, d, i64, i32, vp, i32]
+        lib.pn_jerk.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, i32]
+        lib.pn_step_hermite.argtypes = [vp, vp, vp, i64, d, d, d, d, i64, vp, i32]
         lib.pn_diagnostics.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, i32]
         lib.pn_step_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, d, i64, i32,
                                         vp, i32]
@@ -143,6 +145,17 @@ def pn_accel_eih(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None
 def pn_step(pos, vel, mass, G, c, eps, dt, nsteps, precision=PN_FP64, stream=None, flags=0):
     return _check(load().pn_step(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps, dt,
                                  int(nsteps), precision, _stream(stream), flags), "pn_step")
+
+
+def pn_jerk(pos, vel, mass, G, c, eps, acc, jerk, stream=None, flags=0):
+    return _check(load().pn_jerk(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps, _ptr(acc),
+                                 _ptr(jerk), _stream(stream), flags), "pn_jerk")
+
+
+def pn_step_hermite(pos, vel, mass, G, c, eps, dt, nsteps, stream=None, flags=0):
+    return _check(load().pn_step_hermite(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
+                                         dt, int(nsteps), _stream(stream), flags),
+                  "pn_step_hermite")
 
 
 def pn_diagnostics(pos, vel, mass, G, c, eps, stream=None, flags=0):

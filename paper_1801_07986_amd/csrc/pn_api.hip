@@ -93,10 +93,20 @@ Shape pick_shape(int Ns, int precision) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t pk, ub, bpart, part, bhpart, status, xs, vs, kx, kv, dpart, out8, total;
+  size_t pk, ub, bpart, part, bhpart, status, xs, vs, kx, kv, dpart, out8, ha, hj, xp, vp, ap,
+      total;
 };
 
-Layout layout_for(int64_t N, const Shape& s, bool rk4) {
+// What a call needs beyond one force evaluation: the RK4 stage arrays, or the
+// jerk sweep's wider packets and partials (dual numbers), or those and the
+// Hermite state.
+enum class Need { EVAL, RK4, JERK, HERMITE };
+
+Layout layout_for(int64_t N, const Shape& s, Need need) {
+  const bool rk4 = need == Need::RK4;
+  const bool dual = need == Need::JERK || need == Need::HERMITE;
+  const bool herm = need == Need::HERMITE;
+  const size_t W = dual ? 2 : 1;
   const size_t Ns = (size_t)(N - 1);
   const size_t nb = (Ns + kBlock - 1) / kBlock;
   Layout L;
@@ -106,11 +116,11 @@ Layout layout_for(int64_t N, const Shape& s, bool rk4) {
     o += align256(bytes);
     return at;
   };
-  L.pk = take(Ns * sizeof(PkF64));
-  L.ub = take(Ns * 4 * sizeof(double));
-  L.bpart = take(nb * 8 * sizeof(double));
-  L.part = take((size_t)s.nsplit * std::max(kNF, kND) * Ns * sizeof(double));
-  L.bhpart = take(((Ns + kEpiStars - 1) / kEpiStars) * 4 * sizeof(double));
+  L.pk = take(Ns * (dual ? sizeof(PkDual) : sizeof(PkF64)));
+  L.ub = take(Ns * 4 * W * sizeof(double));
+  L.bpart = take(nb * 8 * W * sizeof(double));
+  L.part = take((size_t)s.nsplit * std::max<size_t>(kNF * W, kND) * Ns * sizeof(double));
+  L.bhpart = take(((Ns + kEpiStars - 1) / kEpiStars) * 4 * W * sizeof(double));
   L.status = take(sizeof(int));
   L.dpart = take(nb * 10 * sizeof(double));
   L.out8 = take(8 * sizeof(double));
@@ -119,6 +129,11 @@ Layout layout_for(int64_t N, const Shape& s, bool rk4) {
   L.vs = take(rk4 ? n3 : 0);
   L.kx = take(rk4 ? n3 : 0);
   L.kv = take(rk4 ? n3 : 0);
+  L.ha = take(herm ? n3 : 0);
+  L.hj = take(herm ? n3 : 0);
+  L.xp = take(herm ? n3 : 0);
+  L.vp = take(herm ? n3 : 0);
+  L.ap = take(herm ? n3 : 0);
   L.total = o;
   return L;
 }
@@ -128,9 +143,10 @@ struct GraphKey {
   int64_t N = 0;
   double G = 0, c = 0, eps = 0, dt = 0;
   int precision = -1, ipt = 0, ws = 0, nsplit = 0;
+  int scheme = 0;  // 0: Runge-Kutta step, 1: Hermite step
   char* base = nullptr;
   bool operator==(const GraphKey& o) const {
-    return pos == o.pos && vel == o.vel && mass == o.mass && N == o.N && G == o.G &&
+    return scheme == o.scheme && pos == o.pos && vel == o.vel && mass == o.mass && N == o.N && G == o.G &&
            (c == o.c || (std::isinf(c) && std::isinf(o.c))) && eps == o.eps && dt == o.dt &&
            precision == o.precision && ipt == o.ipt && ws == o.ws && nsplit == o.nsplit &&
            base == o.base;
@@ -185,16 +201,16 @@ int dev_state(DevState** out) {
 }
 
 void drop_graph(DevState& d) {
-  if (d.gexec) hipGraphExecDestroy(d.gexec);
-  if (d.graph) hipGraphDestroy(d.graph);
+  if (d.gexec) (void)hipGraphExecDestroy(d.gexec);
+  if (d.graph) (void)hipGraphDestroy(d.graph);
   d.gexec = nullptr;
   d.graph = nullptr;
   d.key = GraphKey();
 }
 
 void drop_batch_graph(DevState& d) {
-  if (d.bgexec) hipGraphExecDestroy(d.bgexec);
-  if (d.bgraph) hipGraphDestroy(d.bgraph);
+  if (d.bgexec) (void)hipGraphExecDestroy(d.bgexec);
+  if (d.bgraph) (void)hipGraphDestroy(d.bgraph);
   d.bgexec = nullptr;
   d.bgraph = nullptr;
   d.bkey = BatchKey();
@@ -257,9 +273,15 @@ struct Ptrs {
   T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
-int launch_prologue(const Sys& s, const Ptrs& P, int precision, hipStream_t st) {
+// precision PN_FP64 / PN_MIXED; dual: the jerk sweep's packets, with the
+// derivatives pos_d (velocities) and vel_d (accelerations).
+int launch_prologue(const Sys& s, const Ptrs& P, int precision, hipStream_t st,
+                    bool dual = false, const double* pos_d = nullptr,
+                    const double* vel_d = nullptr) {
   const int Ns = (int)(s.N - 1);
   ProArgs a;
+  a.pos_d = pos_d;
+  a.vel_d = vel_d;
   a.pos = s.pos;
   a.vel = s.vel;
   a.mass = s.mass;
@@ -271,7 +293,9 @@ int launch_prologue(const Sys& s, const Ptrs& P, int precision, hipStream_t st) 
   a.bpart = P.at<double>(P.L.bpart);
   a.status = P.at<int>(P.L.status);
   const int nb = (Ns + kBlock - 1) / kBlock;
-  if (precision == PN_MIXED)
+  if (dual)
+    hipLaunchKernelGGL(k_prologue<Dual>, dim3(nb), dim3(kBlock), 0, st, a);
+  else if (precision == PN_MIXED)
     hipLaunchKernelGGL(k_prologue<float>, dim3(nb), dim3(kBlock), 0, st, a);
   else
     hipLaunchKernelGGL(k_prologue<double>, dim3(nb), dim3(kBlock), 0, st, a);
@@ -316,6 +340,22 @@ int launch_pair(const Sys& s, const Ptrs& P, const Shape& sh, int precision, int
   return PN_OK;
 }
 
+// The jerk sweep: FP64 dual numbers, one i per lane, four wavefronts per
+// i-range, the j-splits of the evaluation's shape.
+int launch_pair_dual(const Sys& s, const Ptrs& P, const Shape& sh, hipStream_t st) {
+  PairArgs a;
+  a.pk = P.at<void>(P.L.pk);
+  a.Ns = (int)(s.N - 1);
+  a.jchunk = sh.jchunk;
+  a.eps2 = s.eps * s.eps;
+  a.part = P.at<double>(P.L.part);
+  const int iblocks = (a.Ns + 63) / 64;
+  hipLaunchKernelGGL((k_pair<Dual, MODE_FUSED, 1, 4>), dim3(iblocks, sh.nsplit), dim3(kBlock), 0,
+                     st, a);
+  HIPCK(hipGetLastError());
+  return PN_OK;
+}
+
 struct Outs {
   double* acc_newton = nullptr;
   double* phi = nullptr;
@@ -326,6 +366,14 @@ struct Outs {
   int stage = -1;
   double dt = 0.0;
   double *X = nullptr, *V = nullptr, *Xs = nullptr, *Vs = nullptr, *KX = nullptr, *KV = nullptr;
+  double* acc_tot = nullptr;
+  // jerk evaluation (dual): derivatives of the state, jerk output, Hermite update
+  bool dual = false;
+  const double* pos_d = nullptr;
+  const double* vel_d = nullptr;
+  double* jerk = nullptr;
+  int herm = -1;
+  double *HA = nullptr, *HJ = nullptr, *XP = nullptr, *VP = nullptr;
 };
 
 int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o, hipStream_t st) {
@@ -362,9 +410,24 @@ int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o,
   a.Vs = o.Vs;
   a.KX = o.KX;
   a.KV = o.KV;
-  hipLaunchKernelGGL(k_epilogue, dim3(ne), dim3(kBlock), 0, st, a);
-  HIPCK(hipGetLastError());
-  hipLaunchKernelGGL(k_bh_final, dim3(1), dim3(kBlock), 0, st, a);
+  a.acc_tot = o.acc_tot;
+  a.pos_d = o.pos_d;
+  a.vel_d = o.vel_d;
+  a.jerk = o.jerk;
+  a.herm = o.herm;
+  a.HA = o.HA;
+  a.HJ = o.HJ;
+  a.XP = o.XP;
+  a.VP = o.VP;
+  if (o.dual) {
+    hipLaunchKernelGGL(k_epilogue<Dual>, dim3(ne), dim3(kBlock), 0, st, a);
+    HIPCK(hipGetLastError());
+    hipLaunchKernelGGL(k_bh_final<Dual>, dim3(1), dim3(kBlock), 0, st, a);
+  } else {
+    hipLaunchKernelGGL(k_epilogue<double>, dim3(ne), dim3(kBlock), 0, st, a);
+    HIPCK(hipGetLastError());
+    hipLaunchKernelGGL(k_bh_final<double>, dim3(1), dim3(kBlock), 0, st, a);
+  }
   HIPCK(hipGetLastError());
   return PN_OK;
 }
@@ -440,6 +503,55 @@ int enqueue_rk4_step(const Sys& s, const Ptrs& P, const Shape& sh, int precision
   return PN_OK;
 }
 
+// Acceleration and jerk at the state s: an FP64 evaluation writes the total
+// acceleration to acc, then the dual sweep differentiates the force along
+// (dx/dt, dv/dt) = (v, acc).  o carries the dual pass's outputs.
+int enqueue_jerk(const Sys& s, const Ptrs& P, const Shape& sh, double* acc, Outs o,
+                 hipStream_t st) {
+  Outs e;
+  e.acc_tot = acc;
+  int rc = enqueue_eval(s, P, sh, PN_FP64, e, st, nullptr);
+  if (rc) return rc;
+  if ((rc = launch_prologue(s, P, PN_FP64, st, true, s.vel, acc))) return rc;
+  if ((rc = launch_pair_dual(s, P, sh, st))) return rc;
+  o.dual = true;
+  o.pos_d = s.vel;
+  o.vel_d = acc;
+  return launch_epilogue(s, P, sh, o, st);
+}
+
+Outs hermite_outs(const Ptrs& P, double dt, double* X, double* V, int herm) {
+  Outs o;
+  o.herm = herm;
+  o.dt = dt;
+  o.X = X;
+  o.V = V;
+  o.HA = P.at<double>(P.L.ha);
+  o.HJ = P.at<double>(P.L.hj);
+  o.XP = P.at<double>(P.L.xp);
+  o.VP = P.at<double>(P.L.vp);
+  return o;
+}
+
+// First Hermite evaluation: acceleration and jerk at (X, V), first prediction.
+int enqueue_hermite_start(const Sys& s, const Ptrs& P, const Shape& sh, double dt, double* X,
+                          double* V, hipStream_t st) {
+  Sys e = s;
+  e.pos = X;
+  e.vel = V;
+  return enqueue_jerk(e, P, sh, P.at<double>(P.L.ap), hermite_outs(P, dt, X, V, 0), st);
+}
+
+// One Hermite step: evaluate at the prediction (XP, VP), correct (X, V) and
+// predict the next state.
+int enqueue_hermite_step(const Sys& s, const Ptrs& P, const Shape& sh, double dt, double* X,
+                         double* V, hipStream_t st) {
+  Sys e = s;
+  e.pos = P.at<double>(P.L.xp);
+  e.vel = P.at<double>(P.L.vp);
+  return enqueue_jerk(e, P, sh, P.at<double>(P.L.ap), hermite_outs(P, dt, X, V, 1), st);
+}
+
 int finish(DevState& d, const Ptrs& P, hipStream_t st, int flags) {
   (void)d;
   if (flags & PN_ASYNC) return PN_OK;
@@ -462,6 +574,31 @@ int reset_status(const Ptrs& P, hipStream_t st) {
 
 hipStream_t pick_stream(DevState& d, void* stream) {
   return stream ? reinterpret_cast<hipStream_t>(stream) : d.own;
+}
+
+// Replays one captured time step nsteps times on `st`.  The step is captured
+// (on the library's own stream) when key differs from the cached graph's.
+template <typename Enqueue>
+int replay_step(DevState& d, const GraphKey& key, int64_t nsteps, hipStream_t st,
+                Enqueue enqueue_step) {
+  if (!d.gexec || !(key == d.key)) {
+    drop_graph(d);
+    HIPCK(hipStreamSynchronize(d.own));
+    HIPCK(hipStreamBeginCapture(d.own, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_step(d.own);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(d.own, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture", __LINE__);
+    d.graph = g;
+    HIPCK(hipGraphInstantiate(&d.gexec, d.graph, nullptr, nullptr, 0));
+    d.key = key;
+  }
+  for (int64_t k = 0; k < nsteps; ++k) HIPCK(hipGraphLaunch(d.gexec, st));
+  return PN_OK;
 }
 
 // ------------------------------------------------------------------ batched ensembles
@@ -615,7 +752,7 @@ int pn_potential_accel(const double* pos, const double* vel, const double* mass,
   DevState* d;
   if ((rc = dev_state(&d))) return rc;
   const Shape sh = pick_shape((int)(N - 1), PN_FP64);
-  const Layout L = layout_for(N, sh, false);
+  const Layout L = layout_for(N, sh, Need::EVAL);
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
@@ -641,7 +778,7 @@ int pn_correction(const double* pos, const double* vel, const double* mass, int6
   DevState* d;
   if ((rc = dev_state(&d))) return rc;
   const Shape sh = pick_shape((int)(N - 1), PN_FP64);
-  const Layout L = layout_for(N, sh, false);
+  const Layout L = layout_for(N, sh, Need::EVAL);
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
@@ -671,7 +808,7 @@ int pn_accel(const double* pos, const double* vel, const double* mass, int64_t N
   DevState* d;
   if ((rc = dev_state(&d))) return rc;
   const Shape sh = pick_shape((int)(N - 1), precision);
-  const Layout L = layout_for(N, sh, false);
+  const Layout L = layout_for(N, sh, Need::EVAL);
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
@@ -705,7 +842,7 @@ int pn_accel_eih(const double* pos, const double* vel, const double* mass, int64
   if ((rc = dev_state(&d))) return rc;
   // both sweeps run over all N bodies: shapes and scratch sized for N "stars"
   const Shape sh = pick_shape((int)N, precision);
-  const Layout L = layout_for(N + 1, sh, false);
+  const Layout L = layout_for(N + 1, sh, Need::EVAL);
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
@@ -751,7 +888,7 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
   DevState* d;
   if ((rc = dev_state(&d))) return rc;
   const Shape sh = pick_shape((int)(N - 1), precision);
-  const Layout L = layout_for(N, sh, true);
+  const Layout L = layout_for(N, sh, Need::RK4);
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
@@ -782,24 +919,76 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
       key.ws = sh.ws;
       key.nsplit = sh.nsplit;
       key.base = d->base;
-      if (!d->gexec || !(key == d->key)) {
-        drop_graph(*d);
-        // capture on the library's own stream; the graph is launched on `st`
-        HIPCK(hipStreamSynchronize(d->own));
-        HIPCK(hipStreamBeginCapture(d->own, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_rk4_step(s, P, sh, precision, dt, pos, vel, d->own, nullptr);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(d->own, &g);
-        if (rc) {
-          if (g) hipGraphDestroy(g);
-          return rc;
-        }
-        if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture", __LINE__);
-        d->graph = g;
-        HIPCK(hipGraphInstantiate(&d->gexec, d->graph, nullptr, nullptr, 0));
-        d->key = key;
-      }
-      for (int64_t k = 0; k < nsteps; ++k) HIPCK(hipGraphLaunch(d->gexec, st));
+      rc = replay_step(*d, key, nsteps, st, [&](hipStream_t cs) {
+        return enqueue_rk4_step(s, P, sh, precision, dt, pos, vel, cs, nullptr);
+      });
+      if (rc) return rc;
+    }
+  }
+  return finish(*d, P, st, flags & ~PN_TIMING);
+}
+
+int pn_jerk(const double* pos, const double* vel, const double* mass, int64_t N, double G,
+            double c, double eps, double* acc, double* jerk, void* stream, int flags) {
+  int rc = check_system(pos, mass, N, G, c, eps);
+  if (rc) return rc;
+  if (!dptr_ok(vel) || !dptr_ok(acc) || !dptr_ok(jerk)) return PN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState* d;
+  if ((rc = dev_state(&d))) return rc;
+  const Shape sh = pick_shape((int)(N - 1), PN_FP64);
+  const Layout L = layout_for(N, sh, Need::JERK);
+  if ((rc = ensure_scratch(*d, L.total))) return rc;
+  Ptrs P{d->base, L};
+  hipStream_t st = pick_stream(*d, stream);
+  Sys s{pos, vel, mass, N, G, c, eps};
+  if ((rc = reset_status(P, st))) return rc;
+  Outs o;
+  o.jerk = jerk;
+  if ((rc = enqueue_jerk(s, P, sh, acc, o, st))) return rc;
+  return finish(*d, P, st, flags & ~PN_TIMING);
+}
+
+int pn_step_hermite(double* pos, double* vel, const double* mass, int64_t N, double G, double c,
+                    double eps, double dt, int64_t nsteps, void* stream, int flags) {
+  int rc = check_system(pos, mass, N, G, c, eps);
+  if (rc) return rc;
+  if (!dptr_ok(vel) || !std::isfinite(dt) || !(dt > 0.0) || nsteps < 0) return PN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState* d;
+  if ((rc = dev_state(&d))) return rc;
+  const Shape sh = pick_shape((int)(N - 1), PN_FP64);
+  const Layout L = layout_for(N, sh, Need::HERMITE);
+  if ((rc = ensure_scratch(*d, L.total))) return rc;
+  Ptrs P{d->base, L};
+  hipStream_t st = pick_stream(*d, stream);
+  Sys s{pos, vel, mass, N, G, c, eps};
+  if ((rc = reset_status(P, st))) return rc;
+  if (nsteps > 0) {
+    if ((rc = enqueue_hermite_start(s, P, sh, dt, pos, vel, st))) return rc;
+    if (flags & (PN_NOGRAPH | PN_TIMING)) {
+      for (int64_t k = 0; k < nsteps; ++k)
+        if ((rc = enqueue_hermite_step(s, P, sh, dt, pos, vel, st))) return rc;
+    } else {
+      GraphKey key;
+      key.scheme = 1;
+      key.pos = pos;
+      key.vel = vel;
+      key.mass = mass;
+      key.N = N;
+      key.G = G;
+      key.c = c;
+      key.eps = eps;
+      key.dt = dt;
+      key.precision = PN_FP64;
+      key.ipt = sh.ipt;
+      key.ws = sh.ws;
+      key.nsplit = sh.nsplit;
+      key.base = d->base;
+      rc = replay_step(*d, key, nsteps, st, [&](hipStream_t cs) {
+        return enqueue_hermite_step(s, P, sh, dt, pos, vel, cs);
+      });
+      if (rc) return rc;
     }
   }
   return finish(*d, P, st, flags & ~PN_TIMING);
@@ -815,7 +1004,7 @@ int pn_diagnostics(const double* pos, const double* vel, const double* mass, int
   DevState* d;
   if ((rc = dev_state(&d))) return rc;
   const Shape sh = pick_shape((int)(N - 1), PN_FP64);
-  const Layout L = layout_for(N, sh, false);
+  const Layout L = layout_for(N, sh, Need::EVAL);
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
@@ -871,7 +1060,7 @@ int pn_encounters(const double* pos, const double* mass, int64_t N, double r_clo
   const int ns = (Ns + jchunk - 1) / jchunk;
   Shape s2 = sh;
   s2.nsplit = std::max(sh.nsplit, ns);  // scratch for the larger split count
-  Layout L = layout_for(N, s2, false);
+  Layout L = layout_for(N, s2, Need::EVAL);
   const size_t extra = align256((size_t)nb * 2 * sizeof(long long));
   if ((rc = ensure_scratch(*d, L.total + extra))) return rc;
   Ptrs P{d->base, L};
@@ -966,7 +1155,7 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(d->own, &g);
         if (rc) {
-          if (g) hipGraphDestroy(g);
+          if (g) (void)hipGraphDestroy(g);
           return rc;
         }
         if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture", __LINE__);

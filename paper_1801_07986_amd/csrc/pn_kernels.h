@@ -88,6 +88,97 @@ __device__ __forceinline__ double fma_uniform_c(double a, double b, double c) {
 }
 __device__ __forceinline__ float fma_uniform_c(float a, float b, float c) { return fmaf(a, b, c); }
 
+// ---------------------------------------------------------------------------
+// Forward-mode dual number v + d e (e^2 = 0).  Evaluating the force with every
+// input replaced by (value, time derivative along the motion) -- positions
+// (x, v), velocities (v, a) -- yields the acceleration in .v and its exact
+// time derivative, the jerk, in .d (the Hermite scheme of Sec. 4-5 needs
+// both).  Operators are hidden friends, so they never shadow the scalar
+// overloads of fma & co. for plain doubles.
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual() = default;
+  __host__ __device__ constexpr Dual(double x) : v(x), d(0.0) {}
+  __host__ __device__ constexpr Dual(double x, double y) : v(x), d(y) {}
+  friend __device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+  friend __device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+  friend __device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
+  friend __device__ __forceinline__ Dual operator*(Dual a, Dual b) {
+    return {a.v * b.v, fma(a.v, b.d, a.d * b.v)};
+  }
+  friend __device__ __forceinline__ Dual operator*(double s, Dual b) { return {s * b.v, s * b.d}; }
+  friend __device__ __forceinline__ Dual operator*(Dual b, double s) { return {b.v * s, b.d * s}; }
+  friend __device__ __forceinline__ Dual operator/(Dual a, double s) { return {a.v / s, a.d / s}; }
+  __device__ __forceinline__ Dual& operator+=(Dual b) {
+    v += b.v;
+    d += b.d;
+    return *this;
+  }
+  __device__ __forceinline__ Dual& operator*=(double s) {
+    v *= s;
+    d *= s;
+    return *this;
+  }
+  friend __device__ __forceinline__ Dual fma(Dual a, Dual b, Dual c) {
+    return {fma(a.v, b.v, c.v), fma(a.v, b.d, fma(a.d, b.v, c.d))};
+  }
+};
+// d(x^-1/2) = -x^-3/2 dx / 2
+__device__ __forceinline__ Dual rsqrt_t(Dual x) {
+  const double y = rsqrt_f64(x.v);
+  return {y, -0.5 * y * y * y * x.d};
+}
+__device__ __forceinline__ Dual fma_uniform_c(Dual a, Dual b, Dual c) { return fma(a, b, c); }
+
+// Helpers that let the O(N) stages run on double or Dual: a Dual quantity
+// stored in a row of width 2K keeps its value in column k and its derivative
+// in column K + k.
+template <typename T> struct IsDual { static constexpr bool value = false; };
+template <> struct IsDual<Dual> { static constexpr bool value = true; };
+template <typename T> struct Width { static constexpr int n = IsDual<T>::value ? 2 : 1; };
+template <typename T> struct ScalarOf { using type = double; };  // O(N) arithmetic of a sweep type
+template <> struct ScalarOf<Dual> { using type = Dual; };
+template <typename T> struct PosOf { using type = double; };     // position type of a sweep type
+template <> struct PosOf<Dual> { using type = Dual; };
+
+__device__ __forceinline__ double val(double x) { return x; }
+__device__ __forceinline__ double val(Dual x) { return x.v; }
+__device__ __forceinline__ bool finite_s(double x) { return isfinite(x); }
+__device__ __forceinline__ bool finite_s(Dual x) { return isfinite(x.v) && isfinite(x.d); }
+
+// element i of a value array (and, for Dual, of its derivative array)
+template <typename S> __device__ __forceinline__ S ld(const double* v, const double* d, size_t i);
+template <> __device__ __forceinline__ double ld<double>(const double* v, const double*, size_t i) {
+  return v[i];
+}
+template <> __device__ __forceinline__ Dual ld<Dual>(const double* v, const double* d, size_t i) {
+  return Dual(v[i], d[i]);
+}
+// column k of a row holding K quantities
+__device__ __forceinline__ void put(double* row, int k, int, double x) { row[k] = x; }
+__device__ __forceinline__ void put(double* row, int k, int K, Dual x) {
+  row[k] = x.v;
+  row[K + k] = x.d;
+}
+template <typename S> __device__ __forceinline__ S get(const double* row, int k, int K);
+template <> __device__ __forceinline__ double get<double>(const double* row, int k, int) {
+  return row[k];
+}
+template <> __device__ __forceinline__ Dual get<Dual>(const double* row, int k, int K) {
+  return Dual(row[k], row[K + k]);
+}
+
+// Star packet of the jerk sweep: every field with its time derivative.
+struct alignas(16) PkDual {
+  Dual x, y, z, gm, svx, svy, svz, e, hbx, hby, hbz;
+};
+static_assert(sizeof(PkDual) == 176, "packet layout");
+template <> struct PkOf<Dual> { using type = PkDual; };
+__device__ __forceinline__ void clear_pad(PkF64& p) { p.pad = 0.0; }
+__device__ __forceinline__ void clear_pad(PkF32& p) { p.pad0 = p.pad1 = 0.f; }
+__device__ __forceinline__ void clear_pad(PkDual&) {}
+
 // Fixed-order workgroup sum of K doubles per thread; result in lds[k*kBlock].
 template <int K>
 __device__ __forceinline__ void block_sum(const double (&v)[K], double* lds) {
@@ -139,33 +230,42 @@ struct ProArgs {
   const double* mass; // [N]
   int Ns;
   double G, eps2;
-  void* pk;       // [Ns] PkF64 or PkF32
-  double* ub;     // [Ns][4]: u_s, b_s(3)
-  double* bpart;  // [gridDim.x][8]: sum m b (3), sum m u, sum m v (3), 0
+  void* pk;       // [Ns] packets (PkOf<T>)
+  double* ub;     // [Ns][4 W]: u_s, b_s(3)
+  double* bpart;  // [gridDim.x][8 W]: sum m b (3), sum m u, sum m v (3), 0
   int* status;
+  // jerk sweep (T = Dual): time derivatives of pos and vel (the velocity and
+  // the acceleration of the evaluation state)
+  const double* pos_d = nullptr;
+  const double* vel_d = nullptr;
 };
 
+// W = Width<T>::n doubles per quantity (value, and derivative for Dual).
 template <typename T>
 __device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double* lds) {
+  using S = typename ScalarOf<T>::type;
+  constexpr int W = Width<T>::n;
   const int k = blk * kBlock + threadIdx.x;
-  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  S v[7] = {0, 0, 0, 0, 0, 0, 0};
   if (k < a.Ns) {
     const int s = k + 1;
-    const double x0 = a.pos[0], y0 = a.pos[1], z0 = a.pos[2];
-    const double xs = a.pos[3 * s], ys = a.pos[3 * s + 1], zs = a.pos[3 * s + 2];
-    const double dx = xs - x0, dy = ys - y0, dz = zs - z0;
-    const double rinv = rsqrt_f64(fma(dz, dz, fma(dy, dy, fma(dx, dx, a.eps2))));
+    const S x0 = ld<S>(a.pos, a.pos_d, 0), y0 = ld<S>(a.pos, a.pos_d, 1),
+            z0 = ld<S>(a.pos, a.pos_d, 2);
+    const S xs = ld<S>(a.pos, a.pos_d, 3 * s), ys = ld<S>(a.pos, a.pos_d, 3 * s + 1),
+            zs = ld<S>(a.pos, a.pos_d, 3 * s + 2);
+    const S dx = xs - x0, dy = ys - y0, dz = zs - z0;
+    const S rinv = rsqrt_t(fma(dz, dz, fma(dy, dy, fma(dx, dx, S(a.eps2)))));
     const double gM = a.G * a.mass[0];
-    const double u = gM * rinv;
-    const double b3 = u * rinv * rinv;
-    const double bx = b3 * dx, by = b3 * dy, bz = b3 * dz;
-    double vx = 0.0, vy = 0.0, vz = 0.0;
+    const S u = gM * rinv;
+    const S b3 = u * rinv * rinv;
+    const S bx = b3 * dx, by = b3 * dy, bz = b3 * dz;
+    S vx = 0.0, vy = 0.0, vz = 0.0;
     if (a.vel) {
-      vx = a.vel[3 * s];
-      vy = a.vel[3 * s + 1];
-      vz = a.vel[3 * s + 2];
+      vx = ld<S>(a.vel, a.vel_d, 3 * s);
+      vy = ld<S>(a.vel, a.vel_d, 3 * s + 1);
+      vz = ld<S>(a.vel, a.vel_d, 3 * s + 2);
     }
-    const double v2 = fma(vz, vz, fma(vy, vy, vx * vx));
+    const S v2 = fma(vz, vz, fma(vy, vy, vx * vx));
     const double m = a.mass[s];
     using Pk = typename PkOf<T>::type;
     Pk p;
@@ -176,22 +276,17 @@ __device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double
     p.svx = (T)(kSqrt32 * vx);
     p.svy = (T)(kSqrt32 * vy);
     p.svz = (T)(kSqrt32 * vz);
-    p.e = (T)fma(-2.0, v2, u);
+    p.e = (T)fma(S(-2.0), v2, u);
     p.hbx = (T)(-0.5 * bx);
     p.hby = (T)(-0.5 * by);
     p.hbz = (T)(-0.5 * bz);
-    if constexpr (sizeof(T) == 8) {
-      p.pad = 0.0;
-    } else {
-      p.pad0 = 0.f;
-      p.pad1 = 0.f;
-    }
+    clear_pad(p);
     static_cast<Pk*>(a.pk)[k] = p;
-    double* ub = a.ub + 4 * (size_t)k;
-    ub[0] = u;
-    ub[1] = bx;
-    ub[2] = by;
-    ub[3] = bz;
+    double* ub = a.ub + 4 * W * (size_t)k;
+    put(ub, 0, 4, u);
+    put(ub, 1, 4, bx);
+    put(ub, 2, 4, by);
+    put(ub, 3, 4, bz);
     v[0] = m * bx;
     v[1] = m * by;
     v[2] = m * bz;
@@ -200,9 +295,14 @@ __device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double
     v[5] = m * vy;
     v[6] = m * vz;
   }
-  block_sum<7>(v, lds);
-  if (threadIdx.x < 8) {
-    a.bpart[(size_t)blk * 8 + threadIdx.x] = threadIdx.x < 7 ? lds[threadIdx.x * kBlock] : 0.0;
+  double flat[7 * W];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) put(flat, q, 7, v[q]);
+  block_sum<7 * W>(flat, lds);
+  if (threadIdx.x < 8 * W) {
+    // row layout: value columns 0..7, derivative columns 8..15 (Dual)
+    const int q = threadIdx.x & 7, h = threadIdx.x >> 3;
+    a.bpart[(size_t)blk * 8 * W + threadIdx.x] = q < 7 ? lds[(h * 7 + q) * kBlock] : 0.0;
   }
   if (blk == 0 && threadIdx.x == 0) {
     const double M = a.mass[0];
@@ -212,7 +312,7 @@ __device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
-  __shared__ double lds[7 * kBlock];
+  __shared__ double lds[7 * Width<T>::n * kBlock];
   prologue_block<T>(a, blockIdx.x, lds);
 }
 
@@ -226,14 +326,15 @@ __global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
 // order at the end.  Partial sums go to part[split][field][star].
 // T = double: FP64 throughout.  T = float: FP64 coordinate differences, FP32
 // pair arithmetic, FP32 partial sums over tiles of kTile j added into FP64
-// accumulators after each tile.
+// accumulators after each tile.  T = Dual: the FP64 sweep on dual numbers,
+// 2 kNF fields per star (values, then their time derivatives).
 // ---------------------------------------------------------------------------
 struct PairArgs {
   const void* pk;
   int Ns;
   int jchunk;  // j per split
   double eps2;
-  double* part;  // [gridDim.y][kNF][Ns]
+  double* part;  // [gridDim.y][kNF W][Ns]
 };
 
 constexpr int kTile = 64;  // j per FP32 partial-sum tile (mixed precision)
@@ -252,7 +353,7 @@ struct PairAcc {
 
 template <typename T, int IPT>
 struct PairI {  // the i-side operands of one lane
-  double x[IPT], y[IPT], z[IPT];
+  typename PosOf<T>::type x[IPT], y[IPT], z[IPT];
   T kx[IPT], ky[IPT], kz[IPT];  // (4/sqrt(3/2)) v_i
   int idx[IPT];
 };
@@ -260,7 +361,8 @@ struct PairI {  // the i-side operands of one lane
 template <typename T, int MODE, int IPT, bool MASK>
 __device__ __forceinline__ void pair_one(const typename PkOf<T>::type& p, int j, T eps2,
                                          const PairI<T, IPT>& I, PairAcc<T, IPT>& A) {
-  const double xj = p.x, yj = p.y, zj = p.z;
+  using P = typename PosOf<T>::type;
+  const P xj = p.x, yj = p.y, zj = p.z;
   const T gm = p.gm;
 #pragma unroll
   for (int ii = 0; ii < IPT; ++ii) {
@@ -327,25 +429,41 @@ __device__ __forceinline__ void pair_segment(const typename PkOf<T>::type* __res
   }
 }
 
-template <typename T, int IPT>
-__device__ __forceinline__ void acc_flush(const PairAcc<T, IPT>& A, double (&acc)[kNF][IPT]) {
+// acc[f] += x (and acc[kNF + f] += dx/dt for Dual)
+template <int NFO, int IPT>
+__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, float x) {
+  acc[f][ii] += (double)x;
+}
+template <int NFO, int IPT>
+__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, double x) {
+  acc[f][ii] += x;
+}
+template <int NFO, int IPT>
+__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, Dual x) {
+  acc[f][ii] += x.v;
+  acc[kNF + f][ii] += x.d;
+}
+
+template <typename T, int IPT, int NFO>
+__device__ __forceinline__ void acc_flush(const PairAcc<T, IPT>& A, double (&acc)[NFO][IPT]) {
 #pragma unroll
   for (int ii = 0; ii < IPT; ++ii) {
-    acc[F_U][ii] += (double)A.U[ii];
-    acc[F_G][ii] += (double)A.Gx[ii];
-    acc[F_G + 1][ii] += (double)A.Gy[ii];
-    acc[F_G + 2][ii] += (double)A.Gz[ii];
-    acc[F_Q][ii] += (double)A.Qx[ii];
-    acc[F_Q + 1][ii] += (double)A.Qy[ii];
-    acc[F_Q + 2][ii] += (double)A.Qz[ii];
-    acc[F_C2][ii] += (double)A.C2[ii];
-    acc[F_Q7][ii] += (double)A.Q7x[ii];
-    acc[F_Q7 + 1][ii] += (double)A.Q7y[ii];
-    acc[F_Q7 + 2][ii] += (double)A.Q7z[ii];
+    acc_add(acc, F_U, ii, A.U[ii]);
+    acc_add(acc, F_G, ii, A.Gx[ii]);
+    acc_add(acc, F_G + 1, ii, A.Gy[ii]);
+    acc_add(acc, F_G + 2, ii, A.Gz[ii]);
+    acc_add(acc, F_Q, ii, A.Qx[ii]);
+    acc_add(acc, F_Q + 1, ii, A.Qy[ii]);
+    acc_add(acc, F_Q + 2, ii, A.Qz[ii]);
+    acc_add(acc, F_C2, ii, A.C2[ii]);
+    acc_add(acc, F_Q7, ii, A.Q7x[ii]);
+    acc_add(acc, F_Q7 + 1, ii, A.Q7y[ii]);
+    acc_add(acc, F_Q7 + 2, ii, A.Q7z[ii]);
   }
 }
 
 __device__ __forceinline__ bool field_written(int f, int mode) {
+  f %= kNF;  // derivative fields of the jerk sweep follow the value fields
   if (f == F_U) return (mode & MODE_P1) != 0;
   if (f < F_Q) return true;
   return (mode & MODE_P2) != 0;
@@ -354,6 +472,7 @@ __device__ __forceinline__ bool field_written(int f, int mode) {
 template <typename T, int MODE, int IPT, int WS>
 __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
   using Pk = typename PkOf<T>::type;
+  constexpr int NFO = kNF * Width<T>::n;  // output fields per star
   constexpr int LANES = kBlock / WS;  // distinct i-lanes per workgroup
   constexpr int IB = LANES * IPT;     // i-bodies per workgroup
   const Pk* __restrict__ pk = static_cast<const Pk*>(a.pk);
@@ -386,34 +505,34 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
   }
   const T eps2 = (T)a.eps2;
 
-  double acc[kNF][IPT];
+  double acc[NFO][IPT];
 #pragma unroll
-  for (int f = 0; f < kNF; ++f)
+  for (int f = 0; f < NFO; ++f)
 #pragma unroll
     for (int ii = 0; ii < IPT; ++ii) acc[f][ii] = 0.0;
 
   PairAcc<T, IPT> A;
-  if constexpr (sizeof(T) == 8) {
+  if constexpr (sizeof(T) != 4) {
     A.zero();
     pair_segment<T, MODE, IPT>(pk, j0, j1, ilo, ihi, eps2, I, A);
-    acc_flush<T, IPT>(A, acc);
+    acc_flush(A, acc);
   } else {
     for (int t0 = j0; t0 < j1; t0 += kTile) {
       const int t1 = min(j1, t0 + kTile);
       A.zero();
       pair_segment<T, MODE, IPT>(pk, t0, t1, ilo, ihi, eps2, I, A);
-      acc_flush<T, IPT>(A, acc);
+      acc_flush(A, acc);
     }
   }
 
   const size_t plane = (size_t)a.Ns;
-  double* out = a.part + (size_t)sp * kNF * plane;
+  double* out = a.part + (size_t)sp * NFO * plane;
   if constexpr (WS == 1) {
 #pragma unroll
     for (int ii = 0; ii < IPT; ++ii) {
       if (I.idx[ii] < a.Ns) {
 #pragma unroll
-        for (int f = 0; f < kNF; ++f)
+        for (int f = 0; f < NFO; ++f)
           if (field_written(f, MODE)) out[f * plane + I.idx[ii]] = acc[f][ii];
       }
     }
@@ -421,13 +540,13 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
     // fixed-order reduction over the WS wavefronts: waves 1..WS-1 park their
     // sums in LDS, wave 0 adds them to its own in wave order and stores
     // (LDS of WS-1 waves only, so it does not cap the occupancy)
-    __shared__ double red[(WS - 1) * kNF * IPT * 64];
+    __shared__ double red[(WS - 1) * NFO * IPT * 64];
     if (wave > 0) {
 #pragma unroll
-      for (int f = 0; f < kNF; ++f)
+      for (int f = 0; f < NFO; ++f)
 #pragma unroll
         for (int ii = 0; ii < IPT; ++ii)
-          red[(((wave - 1) * kNF + f) * IPT + ii) * 64 + lane] = acc[f][ii];
+          red[(((wave - 1) * NFO + f) * IPT + ii) * 64 + lane] = acc[f][ii];
     }
     __syncthreads();
     if (wave == 0) {
@@ -436,11 +555,11 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
         const int idx = ilo + lane + ii * 64;
         if (idx < a.Ns) {
 #pragma unroll
-          for (int f = 0; f < kNF; ++f) {
+          for (int f = 0; f < NFO; ++f) {
             if (field_written(f, MODE)) {
               double sum = acc[f][ii];
 #pragma unroll
-              for (int w = 1; w < WS; ++w) sum += red[(((w - 1) * kNF + f) * IPT + ii) * 64 + lane];
+              for (int w = 1; w < WS; ++w) sum += red[(((w - 1) * NFO + f) * IPT + ii) * 64 + lane];
               out[f * plane + idx] = sum;
             }
           }
@@ -464,10 +583,10 @@ struct EpiArgs {
   const double* mass;
   int Ns;
   double G, lam, eps2;
-  const double* ub;     // [Ns][4]
-  const double* bpart;  // prologue partials [nbpro][8]
+  const double* ub;     // [Ns][4 W]
+  const double* bpart;  // prologue partials [nbpro][8 W]
   int nbpro;
-  const double* part;  // pair partials [nsplit][kNF][Ns]
+  const double* part;  // pair partials [nsplit][kNF W][Ns]
   int nsplit;
   int newton_only;      // skip every 1PN term
   const double* phi_in; // correction mode: Newtonian potential of all N bodies (else nullptr)
@@ -475,13 +594,23 @@ struct EpiArgs {
   double* acc_newton;   // outputs, [N][3] / [N] (any may be nullptr)
   double* phi;
   double* acc_1pn;
-  double* bhpart;  // [gridDim.x][4]: the massive object's 1PN sum, block partials
+  double* bhpart;  // [gridDim.x][4 W]: the massive object's 1PN sum, block partials
   int nbepi;       // (k_bh_final) number of bhpart rows
   int* status;
   // Runge-Kutta stage update (stage < 0: none)
   int stage;
   double dt;
   double *X, *V, *Xs, *Vs, *KX, *KV;  // [N][3]
+  double* acc_tot = nullptr;  // total acceleration [N][3] (optional)
+  // jerk evaluation (S = Dual): derivatives of pos and vel, and the jerk [N][3]
+  const double* pos_d = nullptr;
+  const double* vel_d = nullptr;
+  double* jerk = nullptr;
+  // Hermite update (herm < 0: none, 0: first evaluation, 1: evaluation at
+  // the predicted state): acceleration and jerk kept between steps, and the
+  // next predicted state, all [N][3]
+  int herm = -1;
+  double *HA = nullptr, *HJ = nullptr, *XP = nullptr, *VP = nullptr;
 };
 
 // Classical RK4 bookkeeping for one body component.  The evaluation state of
@@ -517,55 +646,100 @@ __device__ __forceinline__ void rk4_update(const EpiArgs& a, size_t o, double xv
   }
 }
 
+// Fourth-order Hermite bookkeeping for one body component, from the
+// acceleration ap and jerk jp of the evaluation state.  herm 0 (state
+// (X, V)): keeps a = ap, j = jp; snap and crackle are zero.  herm 1 (state
+// (XP, VP), the prediction): corrector
+//   v' = v + (a + ap) dt/2 + (j - jp) dt^2/12,
+//   x' = x + (v + v') dt/2 + (a - ap) dt^2/12,
+// snap and crackle at the step's end from the Hermite interpolant of a,
+//   k = (12 (a - ap) + 6 dt (j + jp)) / dt^3,
+//   s = (-6 (a - ap) - dt (4 j + 2 jp)) / dt^2 + k dt,
+// then a = ap, j = jp.  Both cases predict the next evaluation state
+//   XP = x + v dt + a dt^2/2 + j dt^3/6 + s dt^4/24 + k dt^5/120,
+//   VP = v + a dt + j dt^2/2 + s dt^3/6 + k dt^4/24.
+// (The velocity-dependent 1PN force is why the predictor carries s and k: a
+// velocity predicted to O(dt^3) only would cap the scheme at third order.)
+__device__ __forceinline__ void hermite_update(const EpiArgs& a, size_t o, double ap, double jp) {
+  const double dt = a.dt, dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
+  double x = a.X[o], v = a.V[o], sn = 0.0, cr = 0.0;
+  if (a.herm == 1) {
+    const double a0 = a.HA[o], j0 = a.HJ[o];
+    const double vn = v + dt / 2.0 * (a0 + ap) + dt2 / 12.0 * (j0 - jp);
+    x = x + dt / 2.0 * (v + vn) + dt2 / 12.0 * (a0 - ap);
+    v = vn;
+    cr = (12.0 * (a0 - ap) + 6.0 * dt * (j0 + jp)) / dt3;
+    sn = (-6.0 * (a0 - ap) - dt * (4.0 * j0 + 2.0 * jp)) / dt2 + cr * dt;
+    a.X[o] = x;
+    a.V[o] = v;
+  }
+  a.HA[o] = ap;
+  a.HJ[o] = jp;
+  a.XP[o] = x + dt * v + dt2 / 2.0 * ap + dt3 / 6.0 * jp + dt4 / 24.0 * sn + dt5 / 120.0 * cr;
+  a.VP[o] = v + dt * ap + dt2 / 2.0 * jp + dt3 / 6.0 * sn + dt4 / 24.0 * cr;
+}
+
 // The massive object's acceleration A0 = a^N_0, potential magnitude V0 = -phi_0
 // and the star momentum P, from the prologue partials (or the caller's inputs).
-__device__ __forceinline__ void bh_quantities(const EpiArgs& a, double* lds, double (&A0)[3],
-                                              double& V0, double (&P)[3]) {
-  double r[7];
-  reduce_rows<7>(a.bpart, a.nbpro, 8, lds, r);
+template <typename S>
+__device__ __forceinline__ void bh_quantities(const EpiArgs& a, double* lds, S (&A0)[3], S& V0,
+                                              S (&P)[3]) {
+  constexpr int K = IsDual<S>::value ? 16 : 7;  // columns read per prologue row
+  double r[K];
+  reduce_rows<K>(a.bpart, a.nbpro, IsDual<S>::value ? 16 : 8, lds, r);
   const double M = a.mass[0];
-  A0[0] = r[0] / M;
-  A0[1] = r[1] / M;
-  A0[2] = r[2] / M;
-  V0 = r[3] / M;
-  P[0] = r[4];
-  P[1] = r[5];
-  P[2] = r[6];
-  if (a.phi_in) {
-    V0 = -a.phi_in[0];
-    A0[0] = a.accN_in[0];
-    A0[1] = a.accN_in[1];
-    A0[2] = a.accN_in[2];
+  A0[0] = get<S>(r, 0, 8) / M;
+  A0[1] = get<S>(r, 1, 8) / M;
+  A0[2] = get<S>(r, 2, 8) / M;
+  V0 = get<S>(r, 3, 8) / M;
+  P[0] = get<S>(r, 4, 8);
+  P[1] = get<S>(r, 5, 8);
+  P[2] = get<S>(r, 6, 8);
+  if constexpr (!IsDual<S>::value) {
+    if (a.phi_in) {
+      V0 = -a.phi_in[0];
+      A0[0] = a.accN_in[0];
+      A0[1] = a.accN_in[1];
+      A0[2] = a.accN_in[2];
+    }
   }
 }
 
 constexpr int kEpiStars = 64;  // stars per epilogue workgroup (4 threads per star reduce the splits)
 
 __device__ __forceinline__ bool epi_field_used(int f, const EpiArgs& a) {
+  f %= kNF;
   if (f == F_U) return a.phi_in == nullptr;  // correction mode: U is not computed
   if (f < F_Q) return true;
   return !a.newton_only;
 }
 
+// S = double: the evaluation; S = Dual: the same arithmetic on dual numbers
+// (acceleration and jerk).
+template <typename S>
 __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double* lds,
                                                double* fsum) {
-  double A0[3], V0, P[3];
-  bh_quantities(a, lds, A0, V0, P);
+  constexpr bool DUAL = IsDual<S>::value;
+  constexpr int W = DUAL ? 2 : 1;
+  constexpr int NFO = kNF * W;
+  S A0[3], V0, P[3];
+  bh_quantities<S>(a, lds, A0, V0, P);
   const double M = a.mass[0];
   const double gM = a.G * M;
-  const double w[3] = {-P[0] / M, -P[1] / M, -P[2] / M};
-  const double x0 = a.pos[0], y0 = a.pos[1], z0 = a.pos[2];
+  const S w[3] = {-P[0] / M, -P[1] / M, -P[2] / M};
+  const S x0 = ld<S>(a.pos, a.pos_d, 0), y0 = ld<S>(a.pos, a.pos_d, 1),
+          z0 = ld<S>(a.pos, a.pos_d, 2);
 
-  // split reduction: thread (g, l) sums fields g, g+4, g+8 of star l, in split order
+  // split reduction: thread (g, l) sums fields g, g+4, g+8, ... of star l, in split order
   {
     const int g = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int k = blk * kEpiStars + l;
     if (k < a.Ns) {
       const size_t plane = (size_t)a.Ns;
-      for (int f = g; f < kNF; f += 4) {
+      for (int f = g; f < NFO; f += 4) {
         double sum = 0.0;
         if (epi_field_used(f, a)) {
-          for (int sp = 0; sp < a.nsplit; ++sp) sum += a.part[((size_t)sp * kNF + f) * plane + k];
+          for (int sp = 0; sp < a.nsplit; ++sp) sum += a.part[((size_t)sp * NFO + f) * plane + k];
         }
         fsum[f * kEpiStars + l] = sum;
       }
@@ -574,135 +748,181 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   __syncthreads();
 
   const int k = blk * kEpiStars + threadIdx.x;
-  double bh[3] = {0.0, 0.0, 0.0};
+  S bh[3] = {0.0, 0.0, 0.0};
   if (threadIdx.x < kEpiStars && k < a.Ns) {
     const int i = k + 1;
-    double sum[kNF];
+    const int t = threadIdx.x;
+    S sum[kNF];
 #pragma unroll
-    for (int f = 0; f < kNF; ++f) sum[f] = fsum[f * kEpiStars + threadIdx.x];
+    for (int f = 0; f < kNF; ++f) {
+      if constexpr (DUAL) sum[f] = S(fsum[f * kEpiStars + t], fsum[(kNF + f) * kEpiStars + t]);
+      else sum[f] = fsum[f * kEpiStars + t];
+    }
     sum[F_C2] *= kSqrt32;  // the sweep accumulates D'/sqrt(3/2)
-    const double* ub = a.ub + 4 * (size_t)k;
-    const double ui = ub[0], bx = ub[1], by = ub[2], bz = ub[3];
+    const double* ub = a.ub + 4 * W * (size_t)k;
+    const S ui = get<S>(ub, 0, 4), bx = get<S>(ub, 1, 4), by = get<S>(ub, 2, 4),
+            bz = get<S>(ub, 3, 4);
     // Newtonian part: g_i - b_i with g_i = -G_i
-    const double aN[3] = {-sum[F_G] - bx, -sum[F_G + 1] - by, -sum[F_G + 2] - bz};
-    double Vi = sum[F_U] + ui;  // -phi_i
-    double a1[3] = {0.0, 0.0, 0.0};
-    const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
-    double vi[3] = {0.0, 0.0, 0.0};
+    const S aN[3] = {-sum[F_G] - bx, -sum[F_G + 1] - by, -sum[F_G + 2] - bz};
+    S Vi = sum[F_U] + ui;  // -phi_i
+    S a1[3] = {0.0, 0.0, 0.0};
+    const S xi = ld<S>(a.pos, a.pos_d, 3 * i), yi = ld<S>(a.pos, a.pos_d, 3 * i + 1),
+            zi = ld<S>(a.pos, a.pos_d, 3 * i + 2);
+    S vi[3] = {0.0, 0.0, 0.0};
     if (!a.newton_only) {
-      vi[0] = a.vel[3 * i];
-      vi[1] = a.vel[3 * i + 1];
-      vi[2] = a.vel[3 * i + 2];
-      const double vi2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
-      double Vphi = Vi;
-      double aNs[3] = {aN[0], aN[1], aN[2]};
-      if (a.phi_in) {  // correction mode: the caller's potential and Newtonian acceleration
-        Vphi = -a.phi_in[i];
-        aNs[0] = a.accN_in[3 * i];
-        aNs[1] = a.accN_in[3 * i + 1];
-        aNs[2] = a.accN_in[3 * i + 2];
+      vi[0] = ld<S>(a.vel, a.vel_d, 3 * i);
+      vi[1] = ld<S>(a.vel, a.vel_d, 3 * i + 1);
+      vi[2] = ld<S>(a.vel, a.vel_d, 3 * i + 2);
+      const S vi2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
+      S Vphi = Vi;
+      S aNs[3] = {aN[0], aN[1], aN[2]};
+      if constexpr (!DUAL) {
+        if (a.phi_in) {  // correction mode: the caller's potential and Newtonian acceleration
+          Vphi = -a.phi_in[i];
+          aNs[0] = a.accN_in[3 * i];
+          aNs[1] = a.accN_in[3 * i + 1];
+          aNs[2] = a.accN_in[3 * i + 2];
+        }
       }
       // Eq. (6) star-star terms: S_i0 G_i + Q_i + C2_i v_i + 7 Q7_i, S_i0 = -v_i^2 + 4 u_i
-      const double Si0 = -vi2 + 4.0 * ui;
-      double q[3];
+      const S Si0 = -vi2 + 4.0 * ui;
+      S q[3];
       for (int c = 0; c < 3; ++c)
         q[c] = Si0 * sum[F_G + c] + sum[F_Q + c] + sum[F_C2] * vi[c] + 7.0 * sum[F_Q7 + c];
       // massive-object partner (Eq. (5) and the G^2 m M / velocity terms of Eq. (6))
-      const double d0[3] = {xi - x0, yi - y0, zi - z0};
-      const double rinv0 = rsqrt_f64(d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2] + a.eps2);
-      const double n0[3] = {d0[0] * rinv0, d0[1] * rinv0, d0[2] * rinv0};
-      const double kk = gM * rinv0 * rinv0;
-      const double vw = vi[0] * w[0] + vi[1] * w[1] + vi[2] * w[2];
-      const double dA = d0[0] * A0[0] + d0[1] * A0[1] + d0[2] * A0[2];
-      const double br = -vi2 + 4.0 * vw + 4.0 * Vphi + V0 + 0.5 * dA;
-      const double n4v = 4.0 * (n0[0] * vi[0] + n0[1] * vi[1] + n0[2] * vi[2]);
-      const double nw = n0[0] * w[0] + n0[1] * w[1] + n0[2] * w[2];
-      const double g7 = 3.5 * gM * rinv0;
+      const S d0[3] = {xi - x0, yi - y0, zi - z0};
+      const S rinv0 = rsqrt_t(d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2] + a.eps2);
+      const S n0[3] = {d0[0] * rinv0, d0[1] * rinv0, d0[2] * rinv0};
+      const S kk = gM * rinv0 * rinv0;
+      const S vw = vi[0] * w[0] + vi[1] * w[1] + vi[2] * w[2];
+      const S dA = d0[0] * A0[0] + d0[1] * A0[1] + d0[2] * A0[2];
+      const S br = -vi2 + 4.0 * vw + 4.0 * Vphi + V0 + 0.5 * dA;
+      const S n4v = 4.0 * (n0[0] * vi[0] + n0[1] * vi[1] + n0[2] * vi[2]);
+      const S nw = n0[0] * w[0] + n0[1] * w[1] + n0[2] * w[2];
+      const S g7 = 3.5 * gM * rinv0;
       for (int c = 0; c < 3; ++c) {
-        const double B = kk * (br * n0[c] + n4v * (vi[c] - w[c]) - 3.0 * nw * vi[c]) + g7 * A0[c];
+        const S B = kk * (br * n0[c] + n4v * (vi[c] - w[c]) - 3.0 * nw * vi[c]) + g7 * A0[c];
         a1[c] = a.lam * (B + q[c]);
       }
       // this star's term of the massive object's 1PN sum (Eqs. (2)-(3))
-      const double Vs = Vphi;
+      const S Vs = Vphi;
       const double gm_s = a.G * a.mass[i];
-      const double ks = gm_s * rinv0 * rinv0;
-      const double n0s[3] = {-n0[0], -n0[1], -n0[2]};
-      const double d0s[3] = {-d0[0], -d0[1], -d0[2]};
-      const double nvs = n0s[0] * vi[0] + n0s[1] * vi[1] + n0s[2] * vi[2];
-      const double dAs = d0s[0] * aNs[0] + d0s[1] * aNs[1] + d0s[2] * aNs[2];
-      const double brs = -2.0 * vi2 + 4.0 * vw + 1.5 * nvs * nvs + 4.0 * V0 + Vs + 0.5 * dAs;
-      const double nws = n0s[0] * w[0] + n0s[1] * w[1] + n0s[2] * w[2];
-      const double g7s = 3.5 * gm_s * rinv0;
+      const S ks = gm_s * rinv0 * rinv0;
+      const S n0s[3] = {-n0[0], -n0[1], -n0[2]};
+      const S d0s[3] = {-d0[0], -d0[1], -d0[2]};
+      const S nvs = n0s[0] * vi[0] + n0s[1] * vi[1] + n0s[2] * vi[2];
+      const S dAs = d0s[0] * aNs[0] + d0s[1] * aNs[1] + d0s[2] * aNs[2];
+      const S brs = -2.0 * vi2 + 4.0 * vw + 1.5 * nvs * nvs + 4.0 * V0 + Vs + 0.5 * dAs;
+      const S nws = n0s[0] * w[0] + n0s[1] * w[1] + n0s[2] * w[2];
+      const S g7s = 3.5 * gm_s * rinv0;
       for (int c = 0; c < 3; ++c)
         bh[c] = ks * (brs * n0s[c] + 3.0 * nvs * vi[c] - 3.0 * nvs * w[c] - 4.0 * nws * vi[c]) +
                 g7s * aNs[c];
     }
     if (a.acc_newton) {
-      a.acc_newton[3 * i] = aN[0];
-      a.acc_newton[3 * i + 1] = aN[1];
-      a.acc_newton[3 * i + 2] = aN[2];
+      a.acc_newton[3 * i] = val(aN[0]);
+      a.acc_newton[3 * i + 1] = val(aN[1]);
+      a.acc_newton[3 * i + 2] = val(aN[2]);
     }
-    if (a.phi) a.phi[i] = -Vi;
+    if (a.phi) a.phi[i] = -val(Vi);
     if (a.acc_1pn) {
-      a.acc_1pn[3 * i] = a1[0];
-      a.acc_1pn[3 * i + 1] = a1[1];
-      a.acc_1pn[3 * i + 2] = a1[2];
+      a.acc_1pn[3 * i] = val(a1[0]);
+      a.acc_1pn[3 * i + 1] = val(a1[1]);
+      a.acc_1pn[3 * i + 2] = val(a1[2]);
     }
-    const double at[3] = {aN[0] + a1[0], aN[1] + a1[1], aN[2] + a1[2]};
-    if (!isfinite(at[0]) || !isfinite(at[1]) || !isfinite(at[2])) atomicOr(a.status, 1);
-    if (a.stage >= 0) {
-      for (int c = 0; c < 3; ++c) rk4_update(a, 3 * (size_t)i + c, vi[c], at[c]);
+    const S at[3] = {aN[0] + a1[0], aN[1] + a1[1], aN[2] + a1[2]};
+    if (a.acc_tot) {
+      for (int c = 0; c < 3; ++c) a.acc_tot[3 * i + c] = val(at[c]);
+    }
+    if (!finite_s(at[0]) || !finite_s(at[1]) || !finite_s(at[2])) atomicOr(a.status, 1);
+    if constexpr (DUAL) {
+      if (a.jerk) {
+        for (int c = 0; c < 3; ++c) a.jerk[3 * i + c] = at[c].d;
+      }
+      if (a.herm >= 0) {
+        for (int c = 0; c < 3; ++c) hermite_update(a, 3 * (size_t)i + c, at[c].v, at[c].d);
+      }
+    } else {
+      if (a.stage >= 0) {
+        for (int c = 0; c < 3; ++c) rk4_update(a, 3 * (size_t)i + c, vi[c], at[c]);
+      }
     }
   }
-  double bhs[3] = {bh[0], bh[1], bh[2]};
-  block_sum<3>(bhs, lds);
-  if (threadIdx.x < 4)
-    a.bhpart[(size_t)blk * 4 + threadIdx.x] = threadIdx.x < 3 ? lds[threadIdx.x * kBlock] : 0.0;
+  double bhs[3 * W];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) put(bhs, c, 3, bh[c]);
+  block_sum<3 * W>(bhs, lds);
+  if (threadIdx.x < 4 * W) {
+    // row layout: values in columns 0..2, derivatives in 4..6 (Dual)
+    const int q = threadIdx.x & 3, h = threadIdx.x >> 2;
+    a.bhpart[(size_t)blk * 4 * W + threadIdx.x] = q < 3 ? lds[(h * 3 + q) * kBlock] : 0.0;
+  }
 }
 
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
-  __shared__ double lds[7 * kBlock];
-  __shared__ double fsum[kNF * kEpiStars];
-  epilogue_block(a, blockIdx.x, lds, fsum);
+  __shared__ double lds[(IsDual<S>::value ? 16 : 7) * kBlock];
+  __shared__ double fsum[kNF * Width<S>::n * kEpiStars];
+  epilogue_block<S>(a, blockIdx.x, lds, fsum);
 }
 
+template <typename S>
 __device__ __forceinline__ void bh_final_block(const EpiArgs& a, double* lds) {
-  double A0[3], V0, P[3];
-  bh_quantities(a, lds, A0, V0, P);
-  double T[3] = {0.0, 0.0, 0.0};
-  if (!a.newton_only) reduce_rows<3>(a.bhpart, a.nbepi, 4, lds, T);
+  constexpr bool DUAL = IsDual<S>::value;
+  constexpr int W = DUAL ? 2 : 1;
+  S A0[3], V0, P[3];
+  bh_quantities<S>(a, lds, A0, V0, P);
+  S T[3] = {0.0, 0.0, 0.0};
+  if (!a.newton_only) {
+    double r[4 * W - 1];  // columns 0..2 (and 4..6: derivatives)
+    reduce_rows<4 * W - 1>(a.bhpart, a.nbepi, 4 * W, lds, r);
+    for (int c = 0; c < 3; ++c) T[c] = get<S>(r, c, 4);
+  }
   if (threadIdx.x == 0) {
-    double a1[3], at[3], v0[3] = {0.0, 0.0, 0.0};
+    S a1[3], at[3], v0[3] = {0.0, 0.0, 0.0};
     for (int c = 0; c < 3; ++c) {
       a1[c] = a.lam * T[c];
       at[c] = A0[c] + a1[c];
     }
     if (!a.newton_only) {
-      v0[0] = a.vel[0];
-      v0[1] = a.vel[1];
-      v0[2] = a.vel[2];
+      v0[0] = ld<S>(a.vel, a.vel_d, 0);
+      v0[1] = ld<S>(a.vel, a.vel_d, 1);
+      v0[2] = ld<S>(a.vel, a.vel_d, 2);
     }
     if (a.acc_newton) {
-      a.acc_newton[0] = A0[0];
-      a.acc_newton[1] = A0[1];
-      a.acc_newton[2] = A0[2];
+      a.acc_newton[0] = val(A0[0]);
+      a.acc_newton[1] = val(A0[1]);
+      a.acc_newton[2] = val(A0[2]);
     }
-    if (a.phi) a.phi[0] = -V0;
+    if (a.phi) a.phi[0] = -val(V0);
     if (a.acc_1pn) {
-      a.acc_1pn[0] = a1[0];
-      a.acc_1pn[1] = a1[1];
-      a.acc_1pn[2] = a1[2];
+      a.acc_1pn[0] = val(a1[0]);
+      a.acc_1pn[1] = val(a1[1]);
+      a.acc_1pn[2] = val(a1[2]);
     }
-    if (!isfinite(at[0]) || !isfinite(at[1]) || !isfinite(at[2])) atomicOr(a.status, 1);
-    if (a.stage >= 0) {
-      for (int c = 0; c < 3; ++c) rk4_update(a, (size_t)c, v0[c], at[c]);
+    if (a.acc_tot) {
+      for (int c = 0; c < 3; ++c) a.acc_tot[c] = val(at[c]);
+    }
+    if (!finite_s(at[0]) || !finite_s(at[1]) || !finite_s(at[2])) atomicOr(a.status, 1);
+    if constexpr (DUAL) {
+      if (a.jerk) {
+        for (int c = 0; c < 3; ++c) a.jerk[c] = at[c].d;
+      }
+      if (a.herm >= 0) {
+        for (int c = 0; c < 3; ++c) hermite_update(a, (size_t)c, at[c].v, at[c].d);
+      }
+    } else {
+      if (a.stage >= 0) {
+        for (int c = 0; c < 3; ++c) rk4_update(a, (size_t)c, v0[c], at[c]);
+      }
     }
   }
 }
 
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_bh_final(EpiArgs a) {
-  __shared__ double lds[7 * kBlock];
-  bh_final_block(a, lds);
+  __shared__ double lds[(IsDual<S>::value ? 16 : 7) * kBlock];
+  bh_final_block<S>(a, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1232,13 +1452,13 @@ __global__ __launch_bounds__(kBlock) void k_epilogue_batched(BatchArgs b) {
   __shared__ double fsum[kNF * kEpiStars];
   const int r = batch_rank(b.pre, b.n_sys, blockIdx.x);
   const SysDev S = b.sys[b.order[r]];
-  epilogue_block(batch_epi_args(b, S), blockIdx.x - b.pre[r], lds, fsum);
+  epilogue_block<double>(batch_epi_args(b, S), blockIdx.x - b.pre[r], lds, fsum);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bh_final_batched(BatchArgs b) {
   __shared__ double lds[7 * kBlock];
   const SysDev S = b.sys[b.order[blockIdx.x]];
-  bh_final_block(batch_epi_args(b, S), lds);
+  bh_final_block<double>(batch_epi_args(b, S), lds);
 }
 
 }  // namespace pn

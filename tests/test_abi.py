@@ -32,7 +32,7 @@ def test_header_declares_the_entry_points():
     names = _declared()
     for required in ("pn_potential_accel", "pn_correction", "pn_step", "pn_accel", "pn_accel_eih",
                      "pn_diagnostics", "pn_step_batched", "pn_strerror", "pn_release",
-                     "pn_last_timing"):
+                     "pn_last_timing", "pn_jerk", "pn_step_hermite"):
         assert required in names
 
 
@@ -87,6 +87,14 @@ def test_validation_without_device(lib):
     assert lib.pn_encounters(d, d, 2, 0.1, d, None, 0) == EINVAL
     assert lib.pn_encounters(d, d, 16, -0.1, d, None, 0) == EINVAL
     assert lib.pn_last_timing(None) == EINVAL
+    # pn_jerk: both outputs required; pn_step_hermite: dt > 0, nsteps >= 0
+    assert lib.pn_jerk(d, d, d, 16, 1.0, 30.0, 0.0, None, d, None, 0) == EINVAL
+    assert lib.pn_jerk(d, d, d, 16, 1.0, 30.0, 0.0, d, None, None, 0) == EINVAL
+    assert lib.pn_jerk(d, None, d, 16, 1.0, 30.0, 0.0, d, d, None, 0) == EINVAL
+    assert lib.pn_step_hermite(d, d, d, 16, 1.0, 30.0, 0.0, 0.0, 1, None, 0) == EINVAL
+    assert lib.pn_step_hermite(d, d, d, 16, 1.0, 30.0, 0.0, -1e-3, 1, None, 0) == EINVAL
+    assert lib.pn_step_hermite(d, d, d, 16, 1.0, 30.0, 0.0, 1e-3, -2, None, 0) == EINVAL
+    assert lib.pn_step_hermite(d, d, d, 1, 1.0, 30.0, 0.0, 1e-3, 1, None, 0) == EINVAL
 
 
 def test_batched_validation_without_device(lib):
