@@ -37,10 +37,16 @@ PEAK_FP64_VALU = 78.6e12  # 256 CUs x 2.4 GHz x 64 FMA lanes x 2 flop
 # FP64 one (above 78.6 TFLOP/s-equivalent), so it is held to the FP32 vector
 # figure of the chip (157.3 TFLOP/s), the stricter denominator.
 PEAK_FP32_VALU = 157.3e12
-# HBM traffic per fused-kernel launch from rocprofv3 PMC runs (FETCH_SIZE +
-# WRITE_SIZE, scaled by the copy-kernel calibration); None until measured for
-# the current kernel.
-TRAFFIC_BYTES = {}
+# HBM bytes per fused-sweep launch from rocprofv3 PMC runs of this file
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch; the factors are what
+# the two counters read for a 512 MiB device copy, --copy-calibration 512).
+# Measured for the kernels as they stand; drop an entry when its kernel changes.
+TRAFFIC_BYTES = {
+    # k_pair<double,3,1,4>, N = 16384, 16 splits: FETCH 11566.9 KiB, WRITE 23582.6 KiB
+    ("plummer_n16384_fp64", "k_pair<double,3,*>"): 47837594,
+    # k_pair<float,3,1,4>, N = 65536: FETCH 30800.1 KiB, WRITE 188669.2 KiB
+    ("plummer_n65536_mixed", "k_pair<float,3,*>"): 256275866,
+}
 
 
 def log(msg: str) -> None:
@@ -58,6 +64,8 @@ def main() -> int:
     ap.add_argument("--table32", action="store_true",
                     help="replicate the paper's Table 3.2 timing protocol instead")
     ap.add_argument("--samples", type=int, default=10, help="samples per N for --table32")
+    ap.add_argument("--hermite", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS fourth-order Hermite steps of the workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB buffer 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -75,6 +83,10 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration(torch, args.copy_calibration)
     pn.load()
+    if args.hermite:
+        print(json.dumps(hermite(pn, torch, inputs, None, args.workload, None, args.hermite)),
+              flush=True)
+        return 0
     if args.table32:
         print(json.dumps(table32(pn, torch, inputs, args.samples, not args.no_cpu)), flush=True)
         return 0
@@ -194,9 +206,11 @@ def hermite(pn, torch, inputs, stream, workload, rk4_ms, steps=50):
     pn.pn_step_hermite(pos, vel, mass, 1.0, w["c"], w["eps"], w["dt"], steps, stream=stream)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
-    log(f"hermite N={N}: {ms:.4f} ms/step (RK4 {rk4_ms:.4f} ms/step)")
-    return {"workload": workload, "N": N, "steps": steps, "ms_per_step": ms,
-            "rk4_ms_per_step": rk4_ms, "hermite_over_rk4_time": ms / rk4_ms}
+    log(f"hermite N={N}: {ms:.4f} ms/step")
+    out = {"workload": workload, "N": N, "steps": steps, "ms_per_step": ms}
+    if rk4_ms:
+        out.update(rk4_ms_per_step=rk4_ms, hermite_over_rk4_time=ms / rk4_ms)
+    return out
 
 
 def ensemble(pn, torch, inputs, stream, steps=2):
