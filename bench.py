@@ -64,6 +64,12 @@ def main() -> int:
     ap.add_argument("--table32", action="store_true",
                     help="replicate the paper's Table 3.2 timing protocol instead")
     ap.add_argument("--samples", type=int, default=10, help="samples per N for --table32")
+    ap.add_argument("--study", nargs="*", metavar="WORKLOAD", default=None,
+                    help="only run the named workloads (default: the 16k, 64k and 256k ones) "
+                         "for their full simulated time: energy/momentum drift, massive-object "
+                         "encounter diagnostics, and for mixed ones an FP64 rerun")
+    ap.add_argument("--dt-div", type=int, default=1,
+                    help="--study: divide the workload's dt by this (same simulated time)")
     ap.add_argument("--hermite", type=int, default=0, metavar="STEPS",
                     help="only time STEPS fourth-order Hermite steps of the workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -83,6 +89,12 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration(torch, args.copy_calibration)
     pn.load()
+    if args.study is not None:
+        names = args.study or ["plummer_n16384_fp64", "plummer_n65536_mixed",
+                               "plummer_n262144_mixed"]
+        for name in names:
+            print(json.dumps(study(pn, torch, inputs, name, args.dt_div)), flush=True)
+        return 0
     if args.hermite:
         print(json.dumps(hermite(pn, torch, inputs, None, args.workload, None, args.hermite)),
               flush=True)
@@ -188,6 +200,75 @@ def secondary(pn, torch, inputs, stream):
         out[name + "_pair_per_s"] = 4.0 * 10 * N * N / dt_wall
         log(f"secondary N={N} {name}: {out[name + '_pair_per_s']:.4e} pair/s")
     out["mixed_over_fp64"] = out["mixed_pair_per_s"] / out["fp64_pair_per_s"]
+    return out
+
+
+def study(pn, torch, inputs, workload, dt_div=1, chunks=10):
+    """A workload run for its full simulated time (RK4, its precision; with
+    dt_div > 1 at dt / dt_div and dt_div times the steps), in `chunks`
+    pieces, recording after each the Eq. (7) energy error, Eq. (8) momentum
+    change and the massive object's encounter diagnostics (nearest star, stars
+    within 10 Schwarzschild radii, largest 1PN/Newton ratio of a
+    massive-object pair); a mixed-precision workload is rerun in FP64 from
+    the same state."""
+    w = inputs.WORKLOADS[workload]
+    N, c, eps = w["N"], w["c"], w["eps"]
+    dt, steps = w["dt"] / dt_div, w["steps"] * dt_div
+    pos0, vel0, mass0 = inputs.plummer_bh(N, w["M_bh"], w["seed"])
+    mass = torch.from_numpy(mass0).cuda()
+    r_close = 10.0 * 2.0 * w["M_bh"] / (c * c)
+    out = {"workload": workload, "N": N, "steps": steps, "dt": dt, "t_end": steps * dt,
+           "r_close_10_schwarzschild": r_close}
+
+    def diag(pos, vel):
+        d = pn.pn_diagnostics(pos, vel, mass, 1.0, c, eps)
+        e = pn.pn_encounters(pos, vel, mass, 1.0, c, r_close)
+        return {"E": d[0] + d[1], "E_N": d[0], "E_1PN": d[1],
+                "P": [d[2] + d[5], d[3] + d[6], d[4] + d[7]],
+                "min_r_bh": e["min_r_bh"], "nearest_to_bh": e["nearest_to_bh"],
+                "n_within_10_rs": e["n_close_bh"],
+                "max_bh_pair_1pn_ratio": e["max_bh_pair_1pn_ratio"],
+                "most_relativistic": e["most_relativistic"], "min_r_pair": e["min_r_pair"]}
+
+    psc = float(np.abs(mass0[:, None] * vel0).sum())
+    precs = [w["precision"]] + (["fp64"] if w["precision"] == "mixed" else [])
+    finals = {}
+    for name in precs:
+        prec = pn.PN_MIXED if name == "mixed" else pn.PN_FP64
+        pos = torch.from_numpy(pos0).cuda()
+        vel = torch.from_numpy(vel0).cuda()
+        d0 = diag(pos, vel)
+        hist, wall, done = [], 0.0, 0
+        for k in range(chunks):
+            n = steps * (k + 1) // chunks - done
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pn.pn_step(pos, vel, mass, 1.0, c, eps, dt, n, prec)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            done += n
+            d = diag(pos, vel)
+            h = {"t": done * dt, "dE_rel": (d["E"] - d0["E"]) / abs(d0["E"]),
+                 "min_r_bh": d["min_r_bh"], "nearest_to_bh": d["nearest_to_bh"],
+                 "max_bh_pair_1pn_ratio": d["max_bh_pair_1pn_ratio"],
+                 "most_relativistic": d["most_relativistic"]}
+            hist.append(h)
+            log(f"study {workload} {name} dt={dt:g}: t={h['t']:.4f} dE/E={h['dE_rel']:+.3e} "
+                f"min_r_bh={h['min_r_bh']:.3e} ratio={h['max_bh_pair_1pn_ratio']:.3e} "
+                f"(#{h['most_relativistic']})")
+        r = {"wall_s": wall, "pair_per_s": 4.0 * steps * float(N) * float(N) / wall,
+             "start": d0, "end": d, "dE_rel": (d["E"] - d0["E"]) / abs(d0["E"]),
+             "dE_1PN_rel": (d["E_1PN"] - d0["E_1PN"]) / abs(d0["E"]),
+             "dP_max_over_sum_m_abs_v": max(abs(a - b) for a, b in zip(d["P"], d0["P"])) / psc,
+             "history": hist}
+        out[name] = r
+        finals[name] = (pos.cpu().numpy(), vel.cpu().numpy())
+    if len(finals) == 2:
+        (pm, vm), (pf, vf) = finals["mixed"], finals["fp64"]
+        out["mixed_vs_fp64_end"] = {
+            "max_abs_dx": float(np.abs(pm - pf).max()),
+            "max_abs_dv": float(np.abs(vm - vf).max()),
+            "dE_rel_difference": out["mixed"]["dE_rel"] - out["fp64"]["dE_rel"]}
     return out
 
 
@@ -354,10 +435,26 @@ def cpu_baseline(pos, vel, mass, G, c, eps, budget_s=12.0):
         t_used += time.perf_counter() - t0
         n_eval += 1
         log(f"cpu oracle eval {n_eval}: {t_used:.2f} s")
+    # one thread: star rows of the same evaluation (each sums over all N bodies;
+    # the massive object's row, an O(N^2) sum of its own, is left out)
+    oracle.set_threads(1)
+    rows = np.arange(1, N, 8, dtype=np.int64)
+    n1, t1 = 0, 0.0
+    while t1 < 4.0 and n1 < 20:
+        t0 = time.perf_counter()
+        oracle.accel_rows(pos, vel, mass, G, c, eps, rows)
+        t1 += time.perf_counter() - t0
+        n1 += 1
+    oracle.set_threads(threads)
+    one = n1 * float(len(rows)) * float(N) / t1
+    log(f"cpu oracle, 1 thread: {one:.4e} pair/s")
     return {"value": n_eval * float(N) * float(N) / t_used, "unit": "pair/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n_eval} full force evaluation(s) of the N={N} workload "
-                      f"({t_used:.1f} s, {threads} OpenMP threads)"}
+                      f"({t_used:.1f} s, {threads} OpenMP threads)",
+            "one_thread": {"value": one, "unit": "pair/s", "cores": 1,
+                           "sample": f"{n1} x {len(rows)} star rows (every 8th) x {N} bodies "
+                                     f"({t1:.1f} s)"}}
 
 
 if __name__ == "__main__":

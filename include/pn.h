@@ -29,8 +29,9 @@
  * - Ownership: the caller owns every argument buffer.  The library owns only
  *   internal scratch, kept per device and grown on demand, and (pn_step) cached
  *   HIP graphs; pn_release() frees both.  No argument pointer is kept after the
- *   call returns, except inside pn_step's cached graph, which is re-captured
- *   when any pointer or parameter changes.
+ *   call returns, except inside the cached step graph of pn_step,
+ *   pn_step_hermite and pn_step_batched, which is re-captured when any pointer
+ *   or parameter changes.
  * - Return codes: PN_OK, or one of the negative codes below.  No C++ exception
  *   crosses the ABI.  Outputs are unspecified after an error, except
  *   PN_ENONFINITE, where all outputs are written.
@@ -135,8 +136,9 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
  * (to rounding) in FP64 by forward-mode differentiation of the evaluation:
  * one FP64 evaluation gives a, then the same sweep on dual numbers (value,
  * derivative) with positions (x, v) and velocities (v, a).  Outputs acc, jerk:
- * [N][3] device arrays, both required; vel[0] enters through the 1PN terms'
- * derivatives only as pn_accel uses it.  FP64 only.
+ * [N][3] device arrays, both required.  vel[0] is used here (the massive
+ * object moves with it, so it enters the derivative of every distance to it),
+ * unlike in pn_accel.  FP64 only.
  */
 int pn_jerk(const double* pos, const double* vel, const double* mass, int64_t N, double G,
             double c, double eps, double* acc, double* jerk, void* stream, int flags);
@@ -173,13 +175,17 @@ int pn_diagnostics(const double* pos, const double* vel, const double* mass, int
  * Close-encounter diagnostics of the kind the paper's test-model figures
  * follow (Sec. 4): distance of the star nearest to the massive object, the
  * number of stars closer to it than r_close (e.g. a multiple of the
- * Schwarzschild radius 2GM/c^2), and the nearest star-star pair.  Unsoftened
- * distances; N >= 3.  out6 (HOST, 6 doubles): [min r_0s, its body index,
- * count with r_0s < r_close, min r_ij, i, j] (i < j, body indices; ties go to
- * the smallest indices).  Always synchronous.
+ * Schwarzschild radius 2GM/c^2), the nearest star-star pair, and how
+ * relativistic the most relativistic massive-object/star pair is: the ratio
+ * of the lambda-term of Eq. (5) to the Newtonian pull,
+ * |(4GM/r - v_s^2) n + 4 (n.v_s) v_s| / c^2 (v_s the star's velocity).
+ * Unsoftened distances; N >= 3; c = inf gives ratio 0.  out8 (HOST, 8
+ * doubles): [min r_0s, its body index, count with r_0s < r_close, min r_ij,
+ * i, j, max ratio, its body index] (i < j, body indices; ties go to the
+ * smallest indices).  Always synchronous.
  */
-int pn_encounters(const double* pos, const double* mass, int64_t N, double r_close, double* out6,
-                  void* stream, int flags);
+int pn_encounters(const double* pos, const double* vel, const double* mass, int64_t N, double G,
+                  double c, double r_close, double* out8, void* stream, int flags);
 
 /*
  * Many independent systems advanced together (each as pn_step would).

@@ -46,7 +46,7 @@ def load():
         lib.pn_correction.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, vp, i32]
         lib.pn_accel.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
         lib.pn_accel_eih.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
-        lib.pn_encounters.argtypes = [vp, vp, i64, d, vp, vp, i32]
+        lib.pn_encounters.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, i32]
         lib.pn_step.argtypes = [vp, vp, vp, i64, d, d, d, d, i64, i32, vp, i32]
         lib.pn_jerk.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, i32]
         lib.pn_step_hermite.argtypes = [vp, vp, vp, i64, d, d, d, d, i64, vp, i32]
@@ -166,13 +166,14 @@ def pn_diagnostics(pos, vel, mass, G, c, eps, stream=None, flags=0):
     return list(out)
 
 
-def pn_encounters(pos, mass, r_close, stream=None, flags=0):
-    out = (ctypes.c_double * 6)()
-    _check(load().pn_encounters(_ptr(pos), _ptr(mass), _n(mass), r_close,
+def pn_encounters(pos, vel, mass, G, c, r_close, stream=None, flags=0):
+    out = (ctypes.c_double * 8)()
+    _check(load().pn_encounters(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, r_close,
                                 ctypes.cast(out, ctypes.c_void_p), _stream(stream), flags),
            "pn_encounters")
     return {"min_r_bh": out[0], "nearest_to_bh": int(out[1]), "n_close_bh": int(out[2]),
-            "min_r_pair": out[3], "pair": (int(out[4]), int(out[5]))}
+            "min_r_pair": out[3], "pair": (int(out[4]), int(out[5])),
+            "max_bh_pair_1pn_ratio": out[6], "most_relativistic": int(out[7])}
 
 
 def pn_step_batched(offsets, G, c, eps, pos, vel, mass, dt, nsteps, precision=PN_FP64,

@@ -1043,10 +1043,13 @@ int pn_diagnostics(const double* pos, const double* vel, const double* mass, int
   return finish(*d, P, st, 0);
 }
 
-int pn_encounters(const double* pos, const double* mass, int64_t N, double r_close, double* out6,
-                  void* stream, int flags) {
+int pn_encounters(const double* pos, const double* vel, const double* mass, int64_t N, double G,
+                  double c, double r_close, double* out8, void* stream, int flags) {
   (void)flags;
-  if (!dptr_ok(pos) || !dptr_ok(mass) || N < 3 || N > ((int64_t)1 << 28) || !out6) return PN_EINVAL;
+  if (!dptr_ok(pos) || !dptr_ok(vel) || !dptr_ok(mass) || N < 3 || N > ((int64_t)1 << 28) ||
+      !out8)
+    return PN_EINVAL;
+  if (!(G > 0.0) || !std::isfinite(G) || std::isnan(c) || !(c > 0.0)) return PN_EINVAL;
   if (!(r_close >= 0.0) || std::isnan(r_close)) return PN_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   DevState* d;
@@ -1070,6 +1073,10 @@ int pn_encounters(const double* pos, const double* mass, int64_t N, double r_clo
   if ((rc = launch_prologue(sys, P, PN_FP64, st))) return rc;  // packets hold the positions
   EncArgs e;
   e.pos = pos;
+  e.vel = vel;
+  e.mass = mass;
+  e.G = G;
+  e.lam = lambda_of(c);
   e.pk = P.at<PkF64>(L.pk);
   e.Ns = Ns;
   e.jchunk = jchunk;
@@ -1086,7 +1093,7 @@ int pn_encounters(const double* pos, const double* mass, int64_t N, double r_clo
   HIPCK(hipGetLastError());
   hipLaunchKernelGGL(k_enc_final, dim3(1), dim3(64), 0, st, e);
   HIPCK(hipGetLastError());
-  HIPCK(hipMemcpyAsync(out6, P.at<double>(L.out8), 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(out8, P.at<double>(L.out8), 8 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   return PN_OK;
 }

@@ -1072,16 +1072,36 @@ __global__ __launch_bounds__(kBlock) void k_diag_final(DiagEpiArgs a) {
 // ---------------------------------------------------------------------------
 struct EncArgs {
   const double* pos;
+  const double* vel;
   const PkF64* pk;  // star packets (positions)
   int Ns, jchunk;
   double r_close2;  // squared radius for the count
+  const double* mass;
+  double G, lam;    // gravitational constant, 1/c^2
   double* part;     // [gridDim.y][2][Ns]: per-star nearest r^2 and partner (as double)
   int nsplit;
-  double* bpart;    // [blocks][4]: nearest BH r^2, its star, close count, nearest pair r^2
+  double* bpart;    // [blocks][6]: nearest BH r^2, its star, close count, nearest pair r^2,
+                    //              largest 1PN/Newton ratio of a BH pair, its star
   long long* bpair; // [blocks][2]: nearest pair (i, j)
   int nb;
-  double* out;      // [6] final
+  double* out;      // [8] final
 };
+
+// Strength of the 1PN term of a star's pair with the massive object: the
+// lambda-part of Eq. (5), (G M / r^2) lambda [(4 G M / r - v^2) n + 4 (n.v) v],
+// over the Newtonian pull G M / r^2 (unsoftened r, the star's own velocity).
+__device__ __forceinline__ double bh_pair_ratio(double dx, double dy, double dz, double r2,
+                                                double vx, double vy, double vz, double gM,
+                                                double lam) {
+  const double r = sqrt(r2);
+  const double nx = dx / r, ny = dy / r, nz = dz / r;
+  const double v2 = vx * vx + vy * vy + vz * vz;
+  const double nv = nx * vx + ny * vy + nz * vz;
+  const double k = 4.0 * gM / r - v2;
+  const double tx = k * nx + 4.0 * nv * vx, ty = k * ny + 4.0 * nv * vy,
+               tz = k * nz + 4.0 * nv * vz;
+  return lam * sqrt(tx * tx + ty * ty + tz * tz);
+}
 
 __device__ __forceinline__ bool enc_less(double r2a, long long ia, double r2b, long long ib) {
   return r2a < r2b || (r2a == r2b && ia < ib);
@@ -1112,17 +1132,20 @@ __global__ __launch_bounds__(kBlock) void k_enc_pair(EncArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_enc_star(EncArgs a) {
-  __shared__ double s_r2[kBlock], s_pr2[kBlock], s_cnt[kBlock];
-  __shared__ long long s_i[kBlock], s_pi[kBlock], s_pj[kBlock];
+  __shared__ double s_r2[kBlock], s_pr2[kBlock], s_cnt[kBlock], s_z[kBlock];
+  __shared__ long long s_i[kBlock], s_pi[kBlock], s_pj[kBlock], s_zi[kBlock];
   const int k = blockIdx.x * kBlock + threadIdx.x;
-  double r2 = INFINITY, pr2 = INFINITY, cnt = 0.0;
-  long long idx = LLONG_MAX, pi_ = LLONG_MAX, pj_ = LLONG_MAX;
+  double r2 = INFINITY, pr2 = INFINITY, cnt = 0.0, z = -1.0;
+  long long idx = LLONG_MAX, pi_ = LLONG_MAX, pj_ = LLONG_MAX, zi = LLONG_MAX;
   if (k < a.Ns) {
     const double dx = a.pos[3 * (k + 1)] - a.pos[0], dy = a.pos[3 * (k + 1) + 1] - a.pos[1],
                  dz = a.pos[3 * (k + 1) + 2] - a.pos[2];
     r2 = dx * dx + dy * dy + dz * dz;
     idx = k + 1;
     cnt = r2 < a.r_close2 ? 1.0 : 0.0;
+    z = bh_pair_ratio(dx, dy, dz, r2, a.vel[3 * (k + 1)], a.vel[3 * (k + 1) + 1],
+                      a.vel[3 * (k + 1) + 2], a.G * a.mass[0], a.lam);
+    zi = k + 1;
     for (int sp = 0; sp < a.nsplit; ++sp) {
       const double* p = a.part + (size_t)sp * 2 * a.Ns + k;
       const long long j = (long long)p[a.Ns];
@@ -1143,6 +1166,8 @@ __global__ __launch_bounds__(kBlock) void k_enc_star(EncArgs a) {
   s_pr2[threadIdx.x] = pr2;
   s_pi[threadIdx.x] = pi_;
   s_pj[threadIdx.x] = pj_;
+  s_z[threadIdx.x] = z;
+  s_zi[threadIdx.x] = zi;
   __syncthreads();
   for (int s = kBlock / 2; s > 0; s >>= 1) {
     const int t = threadIdx.x;
@@ -1160,15 +1185,22 @@ __global__ __launch_bounds__(kBlock) void k_enc_star(EncArgs a) {
         s_pi[t] = s_pi[t + s];
         s_pj[t] = s_pj[t + s];
       }
+      // largest ratio, ties to the smaller index (NaN ratios never win)
+      if (s_z[t + s] > s_z[t] || (s_z[t + s] == s_z[t] && s_zi[t + s] < s_zi[t])) {
+        s_z[t] = s_z[t + s];
+        s_zi[t] = s_zi[t + s];
+      }
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double* b = a.bpart + 4 * (size_t)blockIdx.x;
+    double* b = a.bpart + 6 * (size_t)blockIdx.x;
     b[0] = s_r2[0];
     b[1] = (double)s_i[0];
     b[2] = s_cnt[0];
     b[3] = s_pr2[0];
+    b[4] = s_z[0];
+    b[5] = (double)s_zi[0];
     a.bpair[2 * (size_t)blockIdx.x] = s_pi[0];
     a.bpair[2 * (size_t)blockIdx.x + 1] = s_pj[0];
   }
@@ -1176,10 +1208,15 @@ __global__ __launch_bounds__(kBlock) void k_enc_star(EncArgs a) {
 
 __global__ void k_enc_final(EncArgs a) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double r2 = INFINITY, cnt = 0.0, pr2 = INFINITY;
-  long long idx = LLONG_MAX, pi_ = LLONG_MAX, pj_ = LLONG_MAX;
+  double r2 = INFINITY, cnt = 0.0, pr2 = INFINITY, z = -1.0;
+  long long idx = LLONG_MAX, pi_ = LLONG_MAX, pj_ = LLONG_MAX, zi = LLONG_MAX;
   for (int b = 0; b < a.nb; ++b) {
-    const double* p = a.bpart + 4 * (size_t)b;
+    const double* p = a.bpart + 6 * (size_t)b;
+    const long long bz = (long long)p[5];
+    if (p[4] > z || (p[4] == z && bz < zi)) {
+      z = p[4];
+      zi = bz;
+    }
     const long long bi = (long long)p[1];
     if (enc_less(p[0], bi, r2, idx)) {
       r2 = p[0];
@@ -1199,6 +1236,8 @@ __global__ void k_enc_final(EncArgs a) {
   a.out[3] = sqrt(pr2);
   a.out[4] = (double)pi_;
   a.out[5] = (double)pj_;
+  a.out[6] = z;
+  a.out[7] = (double)zi;
 }
 
 // ---------------------------------------------------------------------------

@@ -5,7 +5,8 @@ energy and momentum (Eqs. (7)-(8)) and the energy error relative to the start,
 the star nearest to the massive object and how many stars lie within
 ``--close`` Schwarzschild radii (2GM/c^2) of it, and the nearest star-star
 pair -- the quantities the paper follows for its test model (Sec. 4: energy
-error, nearest binary, nearest star to the massive object).  All arithmetic
+error, nearest binary, nearest star to the massive object) -- and the largest
+1PN/Newtonian ratio of a massive-object/star pair (Eq. (5)).  All arithmetic
 runs in libpn (pn_step, pn_diagnostics, pn_encounters).
 
 Checkpoints (``--checkpoint PATH``) hold the FP64 state and the run's
@@ -68,7 +69,7 @@ def run(pos, vel, mass, *, G, c, eps, dt, t_end, every, precision, out_path, t0=
     with open(out_path, mode) as f:
         while True:
             d = pn.pn_diagnostics(pos, vel, mass, G, c, eps, stream=stream)
-            enc = pn.pn_encounters(pos, mass, close * r_s, stream=stream)
+            enc = pn.pn_encounters(pos, vel, mass, G, c, close * r_s, stream=stream)
             E = d[0] + d[1]
             rec = {"t": t0 + done * dt, "step": step, "E": E, "E_N": d[0], "E_1PN": d[1],
                    "dE_rel": abs(E - E_ref) / abs(E_ref), "P": [d[2] + d[5], d[3] + d[6],
@@ -78,7 +79,8 @@ def run(pos, vel, mass, *, G, c, eps, dt, t_end, every, precision, out_path, t0=
             f.write(json.dumps(rec) + "\n")
             f.flush()
             _log(f"t={rec['t']:.5f} dE/E={rec['dE_rel']:.3e} min_r_bh={enc['min_r_bh']:.4e} "
-                 f"n_close={enc['n_close_bh']} min_r_pair={enc['min_r_pair']:.3e}")
+                 f"n_close={enc['n_close_bh']} min_r_pair={enc['min_r_pair']:.3e} "
+                 f"max_1pn_ratio={enc['max_bh_pair_1pn_ratio']:.3e}")
             if done >= total:
                 break
             n = min(chunk, total - done)

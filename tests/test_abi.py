@@ -84,8 +84,10 @@ def test_validation_without_device(lib):
     assert lib.pn_set_shape(0, 10, 5, 1, 4, 0) == EINVAL
     assert lib.pn_set_shape(0, 2, 5, 3, 4, 0) == EINVAL
     assert lib.pn_diagnostics(d, d, d, 16, 1.0, 30.0, 0.0, None, None, 0) == EINVAL
-    assert lib.pn_encounters(d, d, 2, 0.1, d, None, 0) == EINVAL
-    assert lib.pn_encounters(d, d, 16, -0.1, d, None, 0) == EINVAL
+    assert lib.pn_encounters(d, d, d, 2, 1.0, 30.0, 0.1, d, None, 0) == EINVAL
+    assert lib.pn_encounters(d, d, d, 16, 1.0, 30.0, -0.1, d, None, 0) == EINVAL
+    assert lib.pn_encounters(d, None, d, 16, 1.0, 30.0, 0.1, d, None, 0) == EINVAL
+    assert lib.pn_encounters(d, d, d, 16, 0.0, 30.0, 0.1, d, None, 0) == EINVAL
     assert lib.pn_last_timing(None) == EINVAL
     # pn_jerk: both outputs required; pn_step_hermite: dt > 0, nsteps >= 0
     assert lib.pn_jerk(d, d, d, 16, 1.0, 30.0, 0.0, None, d, None, 0) == EINVAL

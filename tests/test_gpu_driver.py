@@ -1,7 +1,8 @@
 """Close-encounter diagnostics and the simulation driver.
 
-pn_encounters against a brute-force numpy search (minimum distances to
-rounding, indices and counts exactly); the driver's checkpoint/resume is
+pn_encounters against a brute-force numpy search (minimum distances and the
+largest massive-object pair 1PN/Newton ratio to rounding, indices and counts
+exactly); the driver's checkpoint/resume is
 bitwise identical to an uninterrupted run.
 """
 import json
@@ -32,9 +33,18 @@ def dev(a):
 @pytest.mark.parametrize("N", [3, 100, 3001])
 def test_encounters_brute_force(pn, N):
     pos, vel, mass = inputs.plummer_bh(N, 0.1, 40 + N)
-    r_close = 0.3
-    got = pn.pn_encounters(dev(pos), dev(mass), r_close)
+    r_close, G, c = 0.3, 1.0, 7.0
+    got = pn.pn_encounters(dev(pos), dev(vel), dev(mass), G, c, r_close)
     rb = np.linalg.norm(pos[1:] - pos[0], axis=1)
+    # lambda-term of Eq. (5) over the Newtonian pull, per star
+    n = (pos[1:] - pos[0]) / rb[:, None]
+    v = vel[1:]
+    t = ((4.0 * G * mass[0] / rb - (v * v).sum(1))[:, None] * n
+         + 4.0 * (n * v).sum(1)[:, None] * v)
+    ratio = np.linalg.norm(t, axis=1) / c**2
+    kz = int(np.argmax(ratio))
+    assert got["most_relativistic"] == kz + 1
+    assert abs(got["max_bh_pair_1pn_ratio"] - ratio[kz]) <= 1e-13 * ratio[kz]
     k = int(np.argmin(rb))
     assert got["nearest_to_bh"] == k + 1
     assert abs(got["min_r_bh"] - rb[k]) <= 1e-15 * rb[k]
@@ -45,6 +55,8 @@ def test_encounters_brute_force(pn, N):
     i, j = np.unravel_index(np.argmin(d), d.shape)
     assert tuple(sorted((i + 1, j + 1))) == got["pair"]
     assert abs(got["min_r_pair"] - d[i, j]) <= 1e-15 * d[i, j]
+    newton = pn.pn_encounters(dev(pos), dev(vel), dev(mass), G, float("inf"), r_close)
+    assert newton["max_bh_pair_1pn_ratio"] == 0.0
 
 
 def test_driver_resume_is_bitwise(pn, tmp_path):

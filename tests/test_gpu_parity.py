@@ -201,6 +201,31 @@ def test_step_trajectory_n1024(pn, precision):
         assert dp <= 1e-8 and dv <= 1e-6
 
 
+def test_strong_field_encounter(pn):
+    """The regime the large workloads' plunging stars reach: a star 2 Schwarzschild
+    radii (2GM/c^2 = 2.2e-4) from the massive object, moving at 0.8 c
+    tangentially, inside a Plummer sphere (N = 257, M = 0.1, c = 30,
+    eps = 1e-4).  One evaluation, then 20 RK4 steps of 1e-7, against the oracle."""
+    N, M, c, eps = 257, 0.1, 30.0, 1e-4
+    pos, vel, mass = case(N, 321, M)
+    r_s = 2.0 * G * M / c**2
+    pos[1] = pos[0] + [2.0 * r_s, 0.0, 0.0]
+    vel[1] = [0.0, 0.8 * c, 0.0]
+    aN, phi, a1 = gpu_accel(pn, pos, vel, mass, c, eps, 0)
+    rN, rphi, r1 = oracle.accel(pos, vel, mass, G, c, eps)
+    s = newton_scale(pos, mass, eps)
+    e = body_rel(aN + a1, rN + r1, s)
+    e1 = body_rel(a1, r1, s, 1e-6)
+    print(f"strong field: |a1|/|aN| of the star {np.linalg.norm(r1[1]) / np.linalg.norm(rN[1]):.3f}; "
+          f"max rel total {e.max():.3e}, 1PN {e1.max():.3e}")
+    assert e.max() <= TOL_FP64 and e1.max() <= TOL_FP64_1PN
+    P, V = dev(pos), dev(vel)
+    pn.pn_step(P, V, dev(mass), G, c, eps, 1e-7, 20, 0)
+    rp, rv = oracle.step(pos, vel, mass, G, c, eps, 1e-7, 20)
+    assert np.abs(host(P) - rp).max() <= 1e-14 * np.abs(rp).max()
+    assert (np.linalg.norm(host(V) - rv, axis=1) / np.linalg.norm(rv, axis=1).max()).max() <= 1e-12
+
+
 def test_step_graph_equals_direct_launches(pn):
     pos, vel, mass = case(777, 16)
     outs = []
@@ -269,6 +294,25 @@ def test_full_size_n16384_fp64(pn):
     e = body_rel(aN[rows] + a1[rows], rN + r1, s)
     e1 = body_rel(a1[rows], r1, s, 1e-6)
     print(f"N=16384 fp64: max rel total {e.max():.3e}, 1PN {e1.max():.3e}")
+    assert e.max() <= TOL_FP64 and e1.max() <= TOL_FP64_1PN
+
+
+def test_full_size_n16384_final_state(pn):
+    """The same workload after its 1000 RK4 steps of 1e-4 on the GPU: one
+    evaluation at that (GPU-supplied) state against the oracle's, on the
+    massive object, the 63 stars then nearest to it and 448 random stars."""
+    w = inputs.WORKLOADS["plummer_n16384_fp64"]
+    pos, vel, mass = inputs.plummer_bh(w["N"], w["M_bh"], w["seed"])
+    P, V = dev(pos), dev(vel)
+    pn.pn_step(P, V, dev(mass), G, w["c"], w["eps"], w["dt"], w["steps"], 0)
+    pos, vel = host(P), host(V)
+    aN, phi, a1 = gpu_accel(pn, pos, vel, mass, w["c"], w["eps"], 0)
+    rows = _sample_rows(pos, 63, 448, 2)
+    rN, rphi, r1 = oracle.accel_rows(pos, vel, mass, G, w["c"], w["eps"], rows)
+    s = newton_scale(pos, mass, w["eps"], rows)
+    e = body_rel(aN[rows] + a1[rows], rN + r1, s)
+    e1 = body_rel(a1[rows], r1, s, 1e-6)
+    print(f"N=16384 fp64 at t = 0.1: max rel total {e.max():.3e}, 1PN {e1.max():.3e}")
     assert e.max() <= TOL_FP64 and e1.max() <= TOL_FP64_1PN
 
 
