@@ -730,16 +730,35 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   const S x0 = ld<S>(a.pos, a.pos_d, 0), y0 = ld<S>(a.pos, a.pos_d, 1),
           z0 = ld<S>(a.pos, a.pos_d, 2);
 
-  // split reduction: thread (g, l) sums fields g, g+4, g+8, ... of star l, in split order
+  // split reduction: thread (g, l) sums fields g, g+4, g+8, ... of star l, in
+  // split order; the loads of 16 (then 8) splits are issued together (one
+  // memory latency per batch instead of one per split), then added in order
   {
     const int g = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int k = blk * kEpiStars + l;
     if (k < a.Ns) {
       const size_t plane = (size_t)a.Ns;
+      const size_t sstride = (size_t)NFO * plane;
       for (int f = g; f < NFO; f += 4) {
         double sum = 0.0;
         if (epi_field_used(f, a)) {
-          for (int sp = 0; sp < a.nsplit; ++sp) sum += a.part[((size_t)sp * NFO + f) * plane + k];
+          const double* src = a.part + (size_t)f * plane + k;
+          int sp = 0;
+          for (; sp + 16 <= a.nsplit; sp += 16) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = src[(size_t)(sp + q) * sstride];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sum += v[q];
+          }
+          for (; sp + 8 <= a.nsplit; sp += 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = src[(size_t)(sp + q) * sstride];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sum += v[q];
+          }
+          for (; sp < a.nsplit; ++sp) sum += src[(size_t)sp * sstride];
         }
         fsum[f * kEpiStars + l] = sum;
       }
