@@ -181,7 +181,9 @@ struct DevState {
   size_t bcap = 0;
   hipGraph_t bgraph = nullptr;
   hipGraphExec_t bgexec = nullptr;
-  BatchKey bkey;
+  BatchKey bkey;   // ensemble the cached graph was captured for
+  BatchKey bdesc;  // ensemble whose descriptors are in the batched scratch now
+  bool bdesc_valid = false;
 };
 std::vector<DevState> g_dev;
 
@@ -220,6 +222,7 @@ int ensure_batch_scratch(DevState& d, size_t bytes) {
   if (bytes <= d.bcap) return PN_OK;
   HIPCK(hipDeviceSynchronize());
   drop_batch_graph(d);
+  d.bdesc_valid = false;
   if (d.bbase) HIPCK(hipFree(d.bbase));
   d.bbase = nullptr;
   d.bcap = 0;
@@ -1132,8 +1135,10 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
   key.precision = precision;
   key.base = base;
   const bool graph = !(flags & PN_NOGRAPH);
-  const bool same = d->bgexec && key == d->bkey;
-  if (!same) {
+  // The descriptors in scratch are tracked apart from the cached graph: a
+  // direct-launch call for another ensemble overwrites them while the graph
+  // (captured for the first ensemble) stays cached.
+  if (!(d->bdesc_valid && key == d->bdesc)) {
     // system descriptors, launch order and prefixes (host -> device, once per ensemble)
     HIPCK(hipMemcpyAsync(base + P.o_sys, P.sys.data(), n_sys * sizeof(SysDev),
                          hipMemcpyHostToDevice, st));
@@ -1146,6 +1151,8 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
     HIPCK(hipMemcpyAsync(base + P.o_pre_epi, P.pre_epi.data(), (n_sys + 1) * sizeof(int),
                          hipMemcpyHostToDevice, st));
     HIPCK(hipStreamSynchronize(st));
+    d->bdesc = key;
+    d->bdesc_valid = true;
   }
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, st, status);
   HIPCK(hipGetLastError());
@@ -1154,7 +1161,7 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
       for (int64_t k = 0; k < nsteps; ++k)
         if ((rc = enqueue_batched_step(P, base, mass, pos, vel, dt, precision, st))) return rc;
     } else {
-      if (!same) {
+      if (!(d->bgexec && key == d->bkey)) {
         drop_batch_graph(*d);
         HIPCK(hipStreamSynchronize(d->own));
         HIPCK(hipStreamBeginCapture(d->own, hipStreamCaptureModeThreadLocal));
@@ -1235,6 +1242,7 @@ int pn_release(void) {
     if (d.bbase) (void)hipFree(d.bbase);
     d.bbase = nullptr;
     d.bcap = 0;
+    d.bdesc_valid = false;
     for (hipEvent_t e : d.ev) (void)hipEventDestroy(e);
     d.ev.clear();
     if (d.base) (void)hipFree(d.base);

@@ -120,3 +120,27 @@ def test_batched_invalid_mass(pn):
     with pytest.raises(pn.PNError) as e:
         run_batched(pn, pos, vel, mass, off, SYSTEMS[:3], 1e-4, 1, 0)
     assert e.value.code == pn.PN_EINVAL
+
+
+def test_direct_call_of_another_ensemble_between_graph_replays(pn):
+    """Graph replay of ensemble A, a direct-launch call of a smaller ensemble B
+    (which rewrites the system descriptors in the shared batched scratch),
+    then a replay of A with the same buffers: A must step exactly as before."""
+    big, small = SYSTEMS[2:6], SYSTEMS[:3]
+    pos, vel, mass, off = build_ensemble(big)
+    P, V, Mm = dev(pos), dev(vel), dev(mass)
+    Gs, cs, es = [G] * len(big), [s[2] for s in big], [s[3] for s in big]
+
+    def step_big(flags):
+        P.copy_(dev(pos))
+        V.copy_(dev(vel))
+        pn.pn_step_batched(off, Gs, cs, es, P, V, Mm, 1e-4, 2, 0, flags=flags)
+        return P.cpu().numpy(), V.cpu().numpy()
+
+    ref = step_big(pn.PN_NOGRAPH)
+    first = step_big(0)  # captures A's step graph
+    p2, v2, m2, off2 = build_ensemble(small)
+    run_batched(pn, p2, v2, m2, off2, small, 1e-4, 2, 0, flags=pn.PN_NOGRAPH)
+    again = step_big(0)  # same key as the cached graph
+    for x, y, z in zip(ref, first, again):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
