@@ -95,7 +95,11 @@ def _check(rc: int, name: str) -> int:
     return rc
 
 
-def _ptr(t):
+def _ptr(t, numel=None):
+    """Device pointer of a contiguous float64 CUDA/HIP tensor on the current
+    device.  numel, when given, is the element count the library will access
+    (3N for [N][3] arrays, N for [N]): the C ABI sees only pointers, so a
+    shorter buffer is rejected here rather than read past its end."""
     if t is None:
         return None
     import torch
@@ -103,6 +107,11 @@ def _ptr(t):
     if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() \
             or t.device.type != "cuda":
         raise TypeError("expected a contiguous float64 tensor on the GPU")
+    if t.device.index is not None and t.device.index != torch.cuda.current_device():
+        raise ValueError(f"tensor on {t.device}, but the current device is "
+                         f"cuda:{torch.cuda.current_device()}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got a tensor of shape {tuple(t.shape)}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -113,54 +122,69 @@ def _stream(stream):
 
 
 def _n(mass) -> int:
+    """N from the mass vector (which must be one-dimensional)."""
+    if getattr(mass, "dim", lambda: 1)() != 1:
+        raise ValueError("mass must be a vector of N elements")
     return int(mass.shape[0])
 
 
 def pn_potential_accel(pos, vel, mass, G, c, eps, acc_newton, phi, stream=None, flags=0):
-    return _check(load().pn_potential_accel(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
-                                            _ptr(acc_newton), _ptr(phi), _stream(stream), flags),
+    n = _n(mass)
+    return _check(load().pn_potential_accel(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G,
+                                            c, eps, _ptr(acc_newton, 3 * n), _ptr(phi, n),
+                                            _stream(stream), flags),
                   "pn_potential_accel")
 
 
 def pn_correction(pos, vel, mass, G, c, eps, phi, acc_newton, acc_1pn, stream=None, flags=0):
-    return _check(load().pn_correction(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
-                                       _ptr(phi), _ptr(acc_newton), _ptr(acc_1pn),
-                                       _stream(stream), flags), "pn_correction")
+    n = _n(mass)
+    return _check(load().pn_correction(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c,
+                                       eps, _ptr(phi, n), _ptr(acc_newton, 3 * n),
+                                       _ptr(acc_1pn, 3 * n), _stream(stream), flags),
+                  "pn_correction")
 
 
 def pn_accel(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None, acc_1pn=None,
              stream=None, flags=0):
-    return _check(load().pn_accel(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
-                                  precision, _ptr(acc_newton), _ptr(phi), _ptr(acc_1pn),
-                                  _stream(stream), flags), "pn_accel")
+    n = _n(mass)
+    return _check(load().pn_accel(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c, eps,
+                                  precision, _ptr(acc_newton, 3 * n), _ptr(phi, n),
+                                  _ptr(acc_1pn, 3 * n), _stream(stream), flags), "pn_accel")
 
 
 def pn_accel_eih(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None, acc_1pn=None,
                  stream=None, flags=0):
-    return _check(load().pn_accel_eih(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
-                                      precision, _ptr(acc_newton), _ptr(phi), _ptr(acc_1pn),
-                                      _stream(stream), flags), "pn_accel_eih")
+    n = _n(mass)
+    return _check(load().pn_accel_eih(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c,
+                                      eps, precision, _ptr(acc_newton, 3 * n), _ptr(phi, n),
+                                      _ptr(acc_1pn, 3 * n), _stream(stream), flags),
+                  "pn_accel_eih")
 
 
 def pn_step(pos, vel, mass, G, c, eps, dt, nsteps, precision=PN_FP64, stream=None, flags=0):
-    return _check(load().pn_step(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps, dt,
+    n = _n(mass)
+    return _check(load().pn_step(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c, eps, dt,
                                  int(nsteps), precision, _stream(stream), flags), "pn_step")
 
 
 def pn_jerk(pos, vel, mass, G, c, eps, acc, jerk, stream=None, flags=0):
-    return _check(load().pn_jerk(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps, _ptr(acc),
-                                 _ptr(jerk), _stream(stream), flags), "pn_jerk")
+    n = _n(mass)
+    return _check(load().pn_jerk(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c, eps,
+                                 _ptr(acc, 3 * n), _ptr(jerk, 3 * n), _stream(stream), flags),
+                  "pn_jerk")
 
 
 def pn_step_hermite(pos, vel, mass, G, c, eps, dt, nsteps, stream=None, flags=0):
-    return _check(load().pn_step_hermite(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
-                                         dt, int(nsteps), _stream(stream), flags),
+    n = _n(mass)
+    return _check(load().pn_step_hermite(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c,
+                                         eps, dt, int(nsteps), _stream(stream), flags),
                   "pn_step_hermite")
 
 
 def pn_diagnostics(pos, vel, mass, G, c, eps, stream=None, flags=0):
     out = (ctypes.c_double * 8)()
-    _check(load().pn_diagnostics(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, eps,
+    n = _n(mass)
+    _check(load().pn_diagnostics(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c, eps,
                                  ctypes.cast(out, ctypes.c_void_p), _stream(stream), flags),
            "pn_diagnostics")
     return list(out)
@@ -168,7 +192,8 @@ def pn_diagnostics(pos, vel, mass, G, c, eps, stream=None, flags=0):
 
 def pn_encounters(pos, vel, mass, G, c, r_close, stream=None, flags=0):
     out = (ctypes.c_double * 8)()
-    _check(load().pn_encounters(_ptr(pos), _ptr(vel), _ptr(mass), _n(mass), G, c, r_close,
+    n = _n(mass)
+    _check(load().pn_encounters(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c, r_close,
                                 ctypes.cast(out, ctypes.c_void_p), _stream(stream), flags),
            "pn_encounters")
     return {"min_r_bh": out[0], "nearest_to_bh": int(out[1]), "n_close_bh": int(out[2]),
@@ -184,9 +209,11 @@ def pn_step_batched(offsets, G, c, eps, pos, vel, mass, dt, nsteps, precision=PN
     cc = (ctypes.c_double * n_sys)(*[float(x) for x in c])
     ee = (ctypes.c_double * n_sys)(*[float(x) for x in eps])
     cast = lambda a: ctypes.cast(a, ctypes.c_void_p)  # noqa: E731
-    return _check(load().pn_step_batched(n_sys, cast(off), cast(g), cast(cc), cast(ee), _ptr(pos),
-                                         _ptr(vel), _ptr(mass), dt, int(nsteps), precision,
-                                         _stream(stream), flags), "pn_step_batched")
+    n = int(offsets[-1])
+    return _check(load().pn_step_batched(n_sys, cast(off), cast(g), cast(cc), cast(ee),
+                                         _ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass, n), dt,
+                                         int(nsteps), precision, _stream(stream), flags),
+                  "pn_step_batched")
 
 
 def pn_last_timing():

@@ -79,3 +79,25 @@ def test_driver_resume_is_bitwise(pn, tmp_path):
     a = [json.loads(x) for x in open(tmp_path / "a.jsonl")]
     b = [json.loads(x) for x in open(tmp_path / "b.jsonl")]
     assert a[-1]["E"] == b[-1]["E"] and a[-1]["t"] == b[-1]["t"]
+
+
+def test_binding_rejects_mismatched_sizes(pn):
+    """The C ABI sees only pointers: the binding checks every array against N
+    (from mass) before anything is launched."""
+    pos, vel, mass = inputs.plummer_bh(64, 0.1, 5)
+    P, V, M = dev(pos), dev(vel), dev(mass)
+    short = dev(pos[:-1])
+    out = torch.empty((64, 3), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ValueError):
+        pn.pn_step(short, V, M, 1.0, 30.0, 1e-4, 1e-4, 1)
+    with pytest.raises(ValueError):
+        pn.pn_accel(P, V, M, 1.0, 30.0, 1e-4, 0, out[:-1])
+    with pytest.raises(ValueError):
+        pn.pn_jerk(P, V, M, 1.0, 30.0, 1e-4, out, short)
+    with pytest.raises(ValueError):
+        pn.pn_step_batched([0, 30, 64], [1.0, 1.0], [30.0, 30.0], [1e-4, 1e-4], short, V, M,
+                           1e-4, 1)
+    with pytest.raises(ValueError):
+        pn.pn_diagnostics(P, V, M.reshape(8, 8), 1.0, 30.0, 1e-4)
+    # unchanged inputs: nothing ran
+    assert np.array_equal(P.cpu().numpy(), pos)
