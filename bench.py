@@ -41,11 +41,13 @@ PEAK_FP32_VALU = 157.3e12
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch; the factors are what
 # the two counters read for a 512 MiB device copy, --copy-calibration 512).
 # Measured for the kernels as they stand; drop an entry when its kernel changes.
+# Keyed by (workload, kernel, j-splits): the launch shape comes from the tuned
+# table, so a figure applies only to the kernel and split count it was taken on.
 TRAFFIC_BYTES = {
-    # k_pair<double,3,2,4>, N = 16384, 32 splits: FETCH 11587.3 KiB, WRITE 46109.3 KiB
-    ("plummer_n16384_fp64", "k_pair<double,3,*>"): 70946715,
-    # k_pair<float,3,1,4>, N = 65536: FETCH 30800.1 KiB, WRITE 188669.2 KiB
-    ("plummer_n65536_mixed", "k_pair<float,3,*>"): 256275866,
+    # FETCH 11587.3 KiB, WRITE 46109.3 KiB per launch
+    ("plummer_n16384_fp64", "k_pair<double,3,2,4>", 32): 70946715,
+    # FETCH 30800.1 KiB, WRITE 188669.2 KiB per launch
+    ("plummer_n65536_mixed", "k_pair<float,3,1,4>", 32): 256275866,
 }
 
 
@@ -140,11 +142,13 @@ def main() -> int:
     flops = FLOP_PER_PAIR_FUSED * tm["pairs_per_launch"]
     achieved = flops / avg_s
     peak = PEAK_FP64_VALU if prec == pn.PN_FP64 else PEAK_FP32_VALU
-    kname = "k_pair<double,3,*>" if prec == pn.PN_FP64 else "k_pair<float,3,*>"
-    traffic = TRAFFIC_BYTES.get((args.workload, kname))
+    ipt, ws, nsplit, _ = pn.pn_query_shape(prec, N)
+    kname = f"k_pair<{'double' if prec == pn.PN_FP64 else 'float'},3,{ipt},{ws}>"
+    traffic = TRAFFIC_BYTES.get((args.workload, kname, nsplit))
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                "kernel": kname, "avg_launch_ms": avg_s * 1e3, "launches": tm["launches"],
+                "kernel": kname, "nsplit": nsplit, "avg_launch_ms": avg_s * 1e3,
+                "launches": tm["launches"],
                 "flop_per_pair": FLOP_PER_PAIR_FUSED}
     log(f"pair kernel avg {avg_s * 1e3:.4f} ms over {tm['launches']} launches -> "
         f"{achieved / 1e12:.2f} TFLOP/s ({achieved / peak:.1%} of peak)")

@@ -208,6 +208,15 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
  */
 int pn_set_shape(int precision, int64_t n_min, int64_t n_max, int ipt, int ws, int nsplit);
 
+/*
+ * The launch shape the evaluation of an N-body system would use in the given
+ * precision (tuned table, PN_SHAPE override or default rule; the shape
+ * changes only speed, never the sums): out4 (HOST, 4 ints) = [i-bodies per
+ * lane, wavefronts per i-range, j-splits, i-blocks].  Lets a caller name the
+ * exact sweep kernel it measured.
+ */
+int pn_query_shape(int precision, int64_t N, int* out4);
+
 /* Text for a return code (PN_EDEVICE: the last HIP error seen).  Never NULL. */
 const char* pn_strerror(int code);
 

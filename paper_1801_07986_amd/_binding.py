@@ -20,7 +20,7 @@ PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
 
 EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
            "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape",
-           "pn_accel_eih", "pn_encounters", "pn_jerk", "pn_step_hermite")
+           "pn_accel_eih", "pn_encounters", "pn_jerk", "pn_step_hermite", "pn_query_shape")
 TUNED_PATH = os.path.join(HERE, "tuned_shapes.json")
 
 
@@ -58,6 +58,7 @@ def load():
         lib.pn_last_timing.argtypes = [vp]
         lib.pn_release.argtypes = []
         lib.pn_set_shape.argtypes = [i32, i64, i64, i32, i32, i32]
+        lib.pn_query_shape.argtypes = [i32, i64, vp]
         for name in EXPORTS:
             if name != "pn_strerror":
                 getattr(lib, name).restype = i32
@@ -87,6 +88,14 @@ def install_tuned_shapes(path: str | None = None) -> int:
 
 def pn_set_shape(precision, n_min, n_max, ipt, ws, nsplit):
     return _check(load().pn_set_shape(precision, n_min, n_max, ipt, ws, nsplit), "pn_set_shape")
+
+
+def pn_query_shape(precision, N):
+    """(ipt, ws, nsplit, iblocks) of the sweep an N-body evaluation would launch."""
+    out = (ctypes.c_int * 4)()
+    _check(load().pn_query_shape(precision, int(N), ctypes.cast(out, ctypes.c_void_p)),
+           "pn_query_shape")
+    return tuple(out)
 
 
 def _check(rc: int, name: str) -> int:

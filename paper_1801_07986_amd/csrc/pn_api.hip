@@ -1205,6 +1205,18 @@ int pn_set_shape(int precision, int64_t n_min, int64_t n_max, int ipt, int ws, i
   return PN_OK;
 }
 
+int pn_query_shape(int precision, int64_t N, int* out4) {
+  if (!out4 || N < 2 || N > ((int64_t)1 << 28)) return PN_EINVAL;
+  if (precision != PN_FP64 && precision != PN_MIXED) return PN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const Shape sh = pick_shape((int)(N - 1), precision);
+  out4[0] = sh.ipt;
+  out4[1] = sh.ws;
+  out4[2] = sh.nsplit;
+  out4[3] = sh.iblocks;
+  return PN_OK;
+}
+
 const char* pn_strerror(int code) {
   switch (code) {
     case PN_OK: return "ok";

@@ -135,3 +135,26 @@ def test_binding_rejects_host_tensors():
     x = torch.zeros(4, 3, dtype=torch.float64)
     with pytest.raises(TypeError):
         _binding._ptr(x)
+
+
+def test_query_shape_follows_the_tuned_table(lib):
+    """pn_query_shape is host-only: the shape the library would launch, from
+    the table the binding installs when it loads."""
+    import json
+
+    from paper_1801_07986_amd import _binding
+
+    table = json.load(open(_binding.TUNED_PATH))
+    for e in table["entries"]:
+        prec = 0 if e["precision"] == "fp64" else 1
+        N = e["measured_N"]
+        ipt, ws, nsplit, iblocks = _binding.pn_query_shape(prec, N)
+        assert (ipt, ws) == (e["ipt"], e["ws"])
+        assert iblocks == -(-(N - 1) // (256 // ws * ipt))
+        if e["nsplit"] > 0:
+            assert nsplit == e["nsplit"]
+    EINVAL = -1
+    out = (ctypes.c_int * 4)()
+    assert lib.pn_query_shape(0, 1, ctypes.cast(out, ctypes.c_void_p)) == EINVAL
+    assert lib.pn_query_shape(7, 100, ctypes.cast(out, ctypes.c_void_p)) == EINVAL
+    assert lib.pn_query_shape(0, 100, None) == EINVAL
