@@ -176,6 +176,7 @@ def main() -> int:
         result["secondary"] = secondary(pn, torch, inputs, stream)
         result["hermite"] = hermite(pn, torch, inputs, stream, args.workload,
                                     result["ms_per_step"])
+        result["eih"] = eih(pn, torch, inputs, stream)
         result["ensemble"] = ensemble(pn, torch, inputs, stream)
 
     if not args.no_cpu:
@@ -273,6 +274,37 @@ def study(pn, torch, inputs, workload, dt_div=1, chunks=10):
             "max_abs_dx": float(np.abs(pm - pf).max()),
             "max_abs_dv": float(np.abs(vm - vf).max()),
             "dE_rel_difference": out["mixed"]["dE_rel"] - out["fp64"]["dE_rel"]}
+    return out
+
+
+def eih(pn, torch, inputs, stream, reps=20):
+    """Unrestricted EIH evaluations (every pair at full 1PN order, two sweeps
+    over all N bodies) of the N = 16384 and N = 65536 inputs: pair
+    interactions (N^2 per evaluation) per second, FP64 and mixed, against the
+    limited evaluation of the same input."""
+    out = {}
+    for name in ("plummer_n16384_fp64", "plummer_n65536_mixed"):
+        w = inputs.WORKLOADS[name]
+        N = w["N"]
+        pos0, vel0, mass0 = inputs.plummer_bh(N, w["M_bh"], w["seed"])
+        P, V, M = (torch.from_numpy(a).cuda() for a in (pos0, vel0, mass0))
+        acc = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+        r = {"N": N}
+        for pname, prec in (("fp64", pn.PN_FP64), ("mixed", pn.PN_MIXED)):
+            for kind, fn in (("eih", pn.pn_accel_eih), ("limited", pn.pn_accel)):
+                fn(P, V, M, 1.0, w["c"], w["eps"], prec, acc, stream=stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn(P, V, M, 1.0, w["c"], w["eps"], prec, acc, stream=stream,
+                       flags=pn.PN_ASYNC)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / reps * 1e3
+                r[f"{kind}_{pname}_ms"] = ms
+                r[f"{kind}_{pname}_pair_per_s"] = float(N) * N / (ms * 1e-3)
+            log(f"eih N={N} {pname}: {r[f'eih_{pname}_ms']:.3f} ms/eval "
+                f"(limited {r[f'limited_{pname}_ms']:.3f} ms)")
+        out[name.split("_")[1]] = r
     return out
 
 
