@@ -50,6 +50,17 @@ MUTATIONS = [
      "return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + 2.0 * eps2);"),
     ("rk4_weight", "pos[t] += dt / 6.0 * (kx1[t] + 2.0 * kx2[t] + 2.0 * kx3[t] + kx4[t]);",
      "pos[t] += dt / 6.0 * (kx1[t] + 2.0 * kx2[t] + 1.0 * kx3[t] + 2.0 * kx4[t]);"),
+    ("jerk_richardson_weight", "const double w = (k == 1) ? 8.0 : -1.0;",
+     "const double w = (k == 1) ? 7.0 : -1.0;"),
+    ("jerk_no_velocity_shift", "vs[t] = vel[t] + hh * acc_out[t];", "vs[t] = vel[t];"),
+    ("hermite_corrector_jerk", "dt2 / 12.0 * (j[t] - jp[t]);", "dt2 / 10.0 * (j[t] - jp[t]);"),
+    ("hermite_position_corrector_sign", "dt2 / 12.0 * (a[t] - ap[t]);\n      vel[t] = vn;",
+     "dt2 / 12.0 * (ap[t] - a[t]);\n      vel[t] = vn;"),
+    ("hermite_velocity_predictor_without_snap",
+     "vp[t] = vel[t] + dt * a[t] + dt2 / 2.0 * j[t] + dt3 / 6.0 * sn[t] + dt4 / 24.0 * cr[t];",
+     "vp[t] = vel[t] + dt * a[t] + dt2 / 2.0 * j[t];"),
+    ("hermite_crackle_sign", "+ 6.0 * dt * (j[t] + jp[t])) / dt3;",
+     "- 6.0 * dt * (j[t] + jp[t])) / dt3;"),
 ]
 
 # the pins run against each mutant (the mutation test must not rely on P6's
@@ -65,6 +76,10 @@ PIN_CALLS = [
     lambda m: pins.test_p6_periapsis_advance(m),
     lambda m: pins.test_softening_changes_cross_terms_only_at_order_eps2(m),
     lambda m: pins.test_p10_plummer_softening_closed_form(m),
+    lambda m: pins.test_jerk_newtonian_closed_form(m),
+    lambda m: pins.test_jerk_is_the_time_derivative_along_the_motion(m),
+    lambda m: pins.test_hermite_fourth_order_and_precession(m),
+    lambda m: pins.test_hermite_fourth_order_with_velocity_dependent_force(m),
 ]
 
 
