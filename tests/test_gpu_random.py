@@ -1,0 +1,147 @@
+"""Seeded random systems across the parameter space, every evaluation entry
+point against the oracle.
+
+24 systems with N in [2, 3000], massive-object mass in [1e-3, 10] (stars
+total 1), c in {1, 3, 10, 100, inf} (c = 1: 1PN terms of order one),
+eps in {0, 1e-4, 1e-2}, velocities scaled by 10^U(-1, 0.5), a massive object
+moving or at rest (N = 2: a bound pair, as the one-star sphere would sit on
+the massive object).  |a^1PN|/|a^N| reaches 115 in these draws.  Bounds as in
+the fixed-size parity tests, with the per-body floor (1e-3 of the summed
+Newtonian term magnitude) scaled by 1 + 10 lambda (v_max^2 + max potential),
+the size of what the 1PN brackets multiply: FP64 total 1e-12,
+1PN part 1e-10 (floor 1e-6), mixed total 1e-5; unrestricted EIH 1e-12 on the
+total; three RK4 steps 1e-12; the jerk at c = inf against its closed form
+1e-12; Eq. (7)-(8) diagnostics 1e-12.  The mixed bound is 10x the workload
+tests' 1e-6 because at c = 1 the 1PN sums, evaluated in FP32 (2^-24 per
+operation, ~10 dependent operations per pair term, 64-term FP32 tiles), make
+up nearly all of the total: measured 1.2e-6 at c = 1, eps = 0, N = 1530.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_07986_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+G = 1.0
+
+
+def draw(k):
+    rng = np.random.default_rng(7000 + k)
+    N = int(rng.choice([2, 3, 5, 64, 65, 257]) if k % 3 == 0 else rng.integers(2, 3001))
+    M = float(10.0 ** rng.uniform(-3, 1))
+    c = float(rng.choice([1.0, 3.0, 10.0, 100.0, math.inf]))
+    eps = float(rng.choice([0.0, 1e-4, 1e-2]))
+    if N == 2:  # the recentred one-star sphere sits on the massive object: use a bound pair
+        pos = np.array([[0.0, 0.0, 0.0], [0.3, -0.2, 0.1]])
+        vel = np.array([[0.0, 0.0, 0.0], [0.1, 0.2 * math.sqrt(G * M), -0.1]])
+        mass = np.array([M, 1.0])
+    else:
+        pos, vel, mass = inputs.plummer_bh(N, M, 7000 + k)
+    vel = vel * 10.0 ** rng.uniform(-1, 0.5)
+    if k % 2:
+        vel[0] = rng.normal(scale=0.05, size=3)
+    return N, M, c, eps, pos, vel, mass
+
+
+CASES = list(range(24))
+
+
+@pytest.fixture(scope="module")
+def pn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_07986_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def scale(pos, vel, mass, eps, c):
+    """Summed Newtonian pair-term magnitude per body, times 1 + 10 lambda
+    (v_max^2 + max potential): the size of the terms the 1PN brackets
+    multiply, so that a body whose large 1PN terms cancel is judged against
+    them rather than against the Newtonian scale alone."""
+    d = pos[:, None, :] - pos[None, :, :]
+    R2 = (d * d).sum(-1) + eps * eps
+    np.fill_diagonal(R2, np.inf)
+    s = (G * mass[None, :] / np.where(R2 > 0, R2, np.inf)).sum(1)
+    phi = (G * mass[None, :] / np.sqrt(np.where(R2 > 0, R2, np.inf))).sum(1)
+    lam = 0.0 if math.isinf(c) else 1.0 / c**2
+    return s * (1.0 + 10.0 * lam * ((vel * vel).sum(1).max() + phi.max()))
+
+
+def rel(a, b, s, floor=1e-3):
+    num = np.linalg.norm(a - b, axis=-1)
+    den = np.maximum(np.linalg.norm(b, axis=-1), floor * s)
+    out = np.where(num == 0.0, 0.0, np.inf)
+    np.divide(num, den, out=out, where=den > 0)
+    return out.max()
+
+
+@pytest.mark.parametrize("k", CASES)
+def test_random_system(pn, k):
+    N, M, c, eps, pos, vel, mass = draw(k)
+    print(f"[case] k={k} N={N} M={M:.3g} c={c} eps={eps}", flush=True)
+    s = scale(pos, vel, mass, eps, c)
+    P, V, Mm = dev(pos), dev(vel), dev(mass)
+    aN = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    a1 = torch.empty_like(aN)
+    phi = torch.empty(N, dtype=torch.float64, device="cuda:0")
+
+    rN, rphi, r1 = oracle.accel(pos, vel, mass, G, c, eps)
+    pn.pn_accel(P, V, Mm, G, c, eps, pn.PN_FP64, aN, phi, a1)
+    assert rel(host(aN) + host(a1), rN + r1, s) <= 1e-12
+    assert rel(host(a1), r1, s, 1e-6) <= 1e-10
+    assert np.abs(host(phi) - rphi).max() <= 1e-12 * np.abs(rphi).max()
+
+    pn.pn_accel(P, V, Mm, G, c, eps, pn.PN_MIXED, aN, phi, a1)
+    em = rel(host(aN) + host(a1), rN + r1, s)
+    print(f"mixed total {em:.2e}")
+    assert em <= 1e-5
+
+    eN, _, e1 = oracle.eih2(pos, vel, mass, G, c, eps)
+    pn.pn_accel_eih(P, V, Mm, G, c, eps, pn.PN_FP64, aN, phi, a1)
+    assert rel(host(aN) + host(a1), eN + e1, s) <= 1e-12
+
+    d = np.array(pn.pn_diagnostics(P, V, Mm, G, c, eps))
+    rd = oracle.diagnostics(pos, vel, mass, G, c, eps)
+    assert abs(d[0] + d[1] - rd[0] - rd[1]) <= 1e-12 * (abs(rd[0]) + abs(rd[1]))
+
+    dt = 1e-5
+    pn.pn_step(P, V, Mm, G, c, eps, dt, 3, pn.PN_FP64)
+    rp, rv = oracle.step(pos, vel, mass, G, c, eps, dt, 3)
+    assert np.abs(host(P) - rp).max() <= 1e-12 * np.abs(rp).max()
+    assert np.abs(host(V) - rv).max() <= 1e-12 * np.abs(rv).max() + 1e-300
+
+
+@pytest.mark.parametrize("k", CASES[::3])
+def test_random_newtonian_jerk(pn, k):
+    N, M, c, eps, pos, vel, mass = draw(k)
+    eps = max(eps, 1e-4)
+    print(f"[case] k={k} N={N} M={M:.3g} eps={eps}", flush=True)
+    acc = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
+    jerk = torch.empty_like(acc)
+    pn.pn_jerk(dev(pos), dev(vel), dev(mass), G, math.inf, eps, acc, jerk)
+    d = pos[:, None, :] - pos[None, :, :]
+    dv = vel[:, None, :] - vel[None, :, :]
+    R2 = (d * d).sum(-1) + eps * eps
+    np.fill_diagonal(R2, np.inf)
+    R3 = R2 ** 1.5
+    xv = (d * dv).sum(-1)
+    ref = -(G * mass[None, :, None] * (dv / R3[..., None]
+                                       - 3.0 * (xv / (R3 * R2))[..., None] * d)).sum(1)
+    sj = (G * mass[None, :] * np.linalg.norm(dv, axis=-1) / R3).sum(1)
+    assert rel(host(jerk), ref, sj) <= 1e-12
