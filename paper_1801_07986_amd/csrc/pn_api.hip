@@ -159,11 +159,12 @@ struct BatchKey {
   const void *pos = nullptr, *vel = nullptr, *mass = nullptr;
   double dt = 0;
   int precision = -1;
+  int splits = 0;  // the plan's common split count
   char* base = nullptr;
   bool operator==(const BatchKey& o) const {
     return offsets == o.offsets && G == o.G && c == o.c && eps == o.eps && pos == o.pos &&
            vel == o.vel && mass == o.mass && dt == o.dt && precision == o.precision &&
-           base == o.base;
+           splits == o.splits && base == o.base;
   }
 };
 
@@ -608,6 +609,7 @@ int replay_step(DevState& d, const GraphKey& key, int64_t nsteps, hipStream_t st
 struct BatchPlan {
   std::vector<SysDev> sys;
   std::vector<int> order, pre_pro, pre_pair, pre_epi;
+  int splits = 1;  // common j-split count (before the per-system cap)
   size_t o_sys, o_order, o_pre_pro, o_pre_pair, o_pre_epi, o_pk, o_ub, o_bpart, o_part, o_bhpart,
       o_status, o_xs, o_vs, o_kx, o_kv, total;
   int64_t n_bodies = 0;
@@ -623,8 +625,13 @@ BatchPlan plan_batch(int n_sys, const int64_t* off, const double* G, const doubl
   P.sys.resize(n_sys);
   int64_t tot_iblocks = 0;
   for (int b = 0; b < n_sys; ++b) tot_iblocks += (off[b + 1] - off[b] - 1 + 63) / 64;
-  const int ns_common =
+  int ns_common =
       (int)std::max<int64_t>(1, std::min<int64_t>(16, (16384 + tot_iblocks - 1) / tot_iblocks));
+  if (const char* env = getenv("PN_BATCH_SPLITS")) {  // tuning runs
+    const int v = atoi(env);
+    if (v >= 1 && v <= 64) ns_common = v;
+  }
+  P.splits = ns_common;
   int64_t star0 = 0, part0 = 0;
   int pro0 = 0, epi0 = 0;
   for (int b = 0; b < n_sys; ++b) {
@@ -1133,6 +1140,7 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
   key.mass = mass;
   key.dt = dt;
   key.precision = precision;
+  key.splits = P.splits;
   key.base = base;
   const bool graph = !(flags & PN_NOGRAPH);
   // The descriptors in scratch are tracked apart from the cached graph: a
