@@ -38,7 +38,10 @@
  * - Determinism: identical inputs, sizes and schedule give bitwise-identical
  *   outputs (fixed-order reductions, no floating-point atomics).
  * - Thread safety: calls may come from several host threads; the library
- *   serialises them internally.  Calls on one stream run in call order.
+ *   serialises them internally.  Calls on one stream run in call order; a
+ *   call on a different stream than the previous call first makes its stream
+ *   wait for the previous call's device work (all calls share the library's
+ *   scratch), so the device work of two calls never overlaps, PN_ASYNC or not.
  */
 #ifndef PN_H_
 #define PN_H_

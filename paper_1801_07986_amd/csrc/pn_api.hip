@@ -185,6 +185,10 @@ struct DevState {
   BatchKey bkey;   // ensemble the cached graph was captured for
   BatchKey bdesc;  // ensemble whose descriptors are in the batched scratch now
   bool bdesc_valid = false;
+  // every call's device work shares the scratch above: a call on another
+  // stream than the previous one waits for it (last_ev recorded on last_st)
+  hipEvent_t last_ev = nullptr;
+  hipStream_t last_st = nullptr;
 };
 std::vector<DevState> g_dev;
 
@@ -556,8 +560,24 @@ int enqueue_hermite_step(const Sys& s, const Ptrs& P, const Shape& sh, double dt
   return enqueue_jerk(e, P, sh, P.at<double>(P.L.ap), hermite_outs(P, dt, X, V, 1), st);
 }
 
+// Calls share the per-device scratch, so device work of a call must not
+// overlap the previous call's.  On one stream that is stream order; on a
+// different stream the new call first waits for the previous call's event.
+int order_after_previous(DevState& d, hipStream_t st) {
+  if (d.last_ev && d.last_st != st) HIPCK(hipStreamWaitEvent(st, d.last_ev, 0));
+  return PN_OK;
+}
+
+int mark_call_end(DevState& d, hipStream_t st) {
+  if (!d.last_ev) HIPCK(hipEventCreateWithFlags(&d.last_ev, hipEventDisableTiming));
+  HIPCK(hipEventRecord(d.last_ev, st));
+  d.last_st = st;
+  return PN_OK;
+}
+
 int finish(DevState& d, const Ptrs& P, hipStream_t st, int flags) {
-  (void)d;
+  int rc = mark_call_end(d, st);
+  if (rc) return rc;
   if (flags & PN_ASYNC) return PN_OK;
   int status = 0;
   HIPCK(hipMemcpyAsync(&status, P.at<int>(P.L.status), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -579,6 +599,7 @@ int reset_status(const Ptrs& P, hipStream_t st) {
 hipStream_t pick_stream(DevState& d, void* stream) {
   return stream ? reinterpret_cast<hipStream_t>(stream) : d.own;
 }
+
 
 // Replays one captured time step nsteps times on `st`.  The step is captured
 // (on the library's own stream) when key differs from the cached graph's.
@@ -766,6 +787,7 @@ int pn_potential_accel(const double* pos, const double* vel, const double* mass,
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   Sys s{pos, nullptr, mass, N, G, c, eps};
   if ((rc = reset_status(P, st))) return rc;
   if ((rc = launch_prologue(s, P, PN_FP64, st))) return rc;
@@ -792,6 +814,7 @@ int pn_correction(const double* pos, const double* vel, const double* mass, int6
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   Sys s{pos, vel, mass, N, G, c, eps};
   if ((rc = reset_status(P, st))) return rc;
   if ((rc = launch_prologue(s, P, PN_FP64, st))) return rc;
@@ -822,6 +845,7 @@ int pn_accel(const double* pos, const double* vel, const double* mass, int64_t N
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   Sys s{pos, vel, mass, N, G, c, eps};
   Timer tm;
   tm.d = d;
@@ -856,6 +880,7 @@ int pn_accel_eih(const double* pos, const double* vel, const double* mass, int64
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   if ((rc = reset_status(P, st))) return rc;
   EihArgs e;
   e.pos = pos;
@@ -902,6 +927,7 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   Sys s{pos, vel, mass, N, G, c, eps};
   if ((rc = reset_status(P, st))) return rc;
   const bool timing = (flags & PN_TIMING) != 0;
@@ -951,6 +977,7 @@ int pn_jerk(const double* pos, const double* vel, const double* mass, int64_t N,
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   Sys s{pos, vel, mass, N, G, c, eps};
   if ((rc = reset_status(P, st))) return rc;
   Outs o;
@@ -972,6 +999,7 @@ int pn_step_hermite(double* pos, double* vel, const double* mass, int64_t N, dou
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   Sys s{pos, vel, mass, N, G, c, eps};
   if ((rc = reset_status(P, st))) return rc;
   if (nsteps > 0) {
@@ -1018,6 +1046,7 @@ int pn_diagnostics(const double* pos, const double* vel, const double* mass, int
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   Sys s{pos, vel, mass, N, G, c, eps};
   if ((rc = reset_status(P, st))) return rc;
   if ((rc = launch_prologue(s, P, PN_FP64, st))) return rc;
@@ -1078,6 +1107,7 @@ int pn_encounters(const double* pos, const double* vel, const double* mass, int6
   if ((rc = ensure_scratch(*d, L.total + extra))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   Sys sys{pos, nullptr, mass, N, 1.0, 1.0, 0.0};
   if ((rc = reset_status(P, st))) return rc;
   if ((rc = launch_prologue(sys, P, PN_FP64, st))) return rc;  // packets hold the positions
@@ -1104,6 +1134,7 @@ int pn_encounters(const double* pos, const double* vel, const double* mass, int6
   hipLaunchKernelGGL(k_enc_final, dim3(1), dim3(64), 0, st, e);
   HIPCK(hipGetLastError());
   HIPCK(hipMemcpyAsync(out8, P.at<double>(L.out8), 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+  if ((rc = mark_call_end(*d, st))) return rc;
   HIPCK(hipStreamSynchronize(st));
   return PN_OK;
 }
@@ -1126,6 +1157,7 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
   int rc = dev_state(&d);
   if (rc) return rc;
   hipStream_t st = pick_stream(*d, stream);
+  if ((rc = order_after_previous(*d, st))) return rc;
   const BatchPlan P = plan_batch(n_sys, offsets, G, c, eps);
   if ((rc = ensure_batch_scratch(*d, P.total))) return rc;
   char* base = d->bbase;
@@ -1188,6 +1220,7 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
       for (int64_t k = 0; k < nsteps; ++k) HIPCK(hipGraphLaunch(d->bgexec, st));
     }
   }
+  if ((rc = mark_call_end(*d, st))) return rc;
   if (flags & PN_ASYNC) return PN_OK;
   int hstatus = 0;
   HIPCK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1265,6 +1298,9 @@ int pn_release(void) {
     d.bdesc_valid = false;
     for (hipEvent_t e : d.ev) (void)hipEventDestroy(e);
     d.ev.clear();
+    if (d.last_ev) (void)hipEventDestroy(d.last_ev);
+    d.last_ev = nullptr;
+    d.last_st = nullptr;
     if (d.base) (void)hipFree(d.base);
     d.base = nullptr;
     d.cap = 0;

@@ -341,3 +341,27 @@ def test_full_size_n65536_mixed(pn):
     print(f"N=65536 mixed: max rel total {e.max():.3e} median {np.median(e):.3e}, "
           f"1PN max {e1.max():.3e}")
     assert e.max() <= TOL_MIXED and e1.max() <= TOL_MIXED_1PN
+
+
+def test_async_calls_on_two_streams_do_not_interfere(pn):
+    """Two systems stepped with PN_ASYNC on two streams, back to back (they
+    share the library's scratch): each ends exactly as when stepped alone."""
+    a = case(3000, 31)
+    b = case(2000, 32)
+    alone = []
+    for pos, vel, mass in (a, b):
+        P, V = dev(pos), dev(vel)
+        pn.pn_step(P, V, dev(mass), G, 30.0, 1e-4, 1e-4, 5, 0)
+        alone.append((host(P), host(V)))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    PA, VA, MA = dev(a[0]), dev(a[1]), dev(a[2])
+    PB, VB, MB = dev(b[0]), dev(b[1]), dev(b[2])
+    torch.cuda.synchronize()
+    for _ in range(3):
+        pn.pn_step(PA, VA, MA, G, 30.0, 1e-4, 1e-4, 1, 0, stream=s1, flags=pn.PN_ASYNC)
+        pn.pn_step(PB, VB, MB, G, 30.0, 1e-4, 1e-4, 1, 0, stream=s2, flags=pn.PN_ASYNC)
+    pn.pn_step(PA, VA, MA, G, 30.0, 1e-4, 1e-4, 2, 0, stream=s1, flags=pn.PN_ASYNC)
+    pn.pn_step(PB, VB, MB, G, 30.0, 1e-4, 1e-4, 2, 0, stream=s2, flags=pn.PN_ASYNC)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(PA), alone[0][0]) and np.array_equal(host(VA), alone[0][1])
+    assert np.array_equal(host(PB), alone[1][0]) and np.array_equal(host(VB), alone[1][1])
