@@ -49,8 +49,12 @@ def load_checkpoint(path):
 
 
 def run(pos, vel, mass, *, G, c, eps, dt, t_end, every, precision, out_path, t0=0.0, step0=0,
-        E_ref=None, close=10.0, checkpoint=None, meta=None, stream=None):
-    """Advance (pos, vel) [torch, on the GPU] from t0 to t_end; returns the last record."""
+        E_ref=None, close=10.0, checkpoint=None, meta=None, stream=None, integrator="rk4"):
+    """Advance (pos, vel) [torch, on the GPU] from t0 to t_end; returns the last record.
+
+    integrator "rk4" (pn_step, FP64 or mixed) or "hermite" (pn_step_hermite,
+    FP64; each chunk between records starts the scheme afresh from the
+    acceleration and jerk of its first state)."""
     import paper_1801_07986_amd as pn
 
     prec = pn.PN_MIXED if precision == "mixed" else pn.PN_FP64
@@ -63,7 +67,7 @@ def run(pos, vel, mass, *, G, c, eps, dt, t_end, every, precision, out_path, t0=
         E_ref = d0[0] + d0[1]
     meta = dict(meta or {})
     meta.update(G=G, c=c, eps=eps, dt=dt, precision=precision, E_ref=E_ref, every=every,
-                close=close)
+                close=close, integrator=integrator)
     done, step, rec = 0, step0, None
     mode = "a" if step0 > 0 else "w"
     with open(out_path, mode) as f:
@@ -84,7 +88,10 @@ def run(pos, vel, mass, *, G, c, eps, dt, t_end, every, precision, out_path, t0=
             if done >= total:
                 break
             n = min(chunk, total - done)
-            pn.pn_step(pos, vel, mass, G, c, eps, dt, n, prec, stream=stream)
+            if integrator == "hermite":
+                pn.pn_step_hermite(pos, vel, mass, G, c, eps, dt, n, stream=stream)
+            else:
+                pn.pn_step(pos, vel, mass, G, c, eps, dt, n, prec, stream=stream)
             done += n
             step += n
             if checkpoint:
@@ -107,6 +114,8 @@ def main(argv=None):
     ap.add_argument("--every", type=float, default=0.125)
     ap.add_argument("--close", type=float, default=10.0, help="count radius in 2GM/c^2")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--integrator", choices=("rk4", "hermite"), default=None,
+                    help="default rk4; on --resume, the checkpoint's unless given")
     ap.add_argument("--out", required=True)
     ap.add_argument("--checkpoint", default=None)
     ap.add_argument("--resume", default=None)
@@ -122,6 +131,8 @@ def main(argv=None):
         pos, vel, mass, meta = load_checkpoint(args.resume)
         t0, step0, E_ref = meta["t"], meta["step"], meta["E_ref"]
         args.c, args.eps, dt = meta["c"], meta["eps"], meta["dt"]
+        if args.integrator is None:
+            args.integrator = meta.get("integrator", "rk4")
         _log(f"resuming from t={t0} (step {step0})")
     elif args.model == "cold":
         pos, vel, mass = inputs.cold_sphere_bh(args.n_stars, args.seed)
@@ -131,12 +142,13 @@ def main(argv=None):
     P = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
     V = torch.from_numpy(np.ascontiguousarray(vel)).to(dev)
     Mm = torch.from_numpy(np.ascontiguousarray(mass)).to(dev)
-    _log(f"model={args.model} N={len(mass)} dt=2^{args.dt_log2} c={args.c} eps={args.eps} "
-         f"t: {t0} -> {args.t_end}")
+    _log(f"model={args.model} N={len(mass)} dt={dt:g} c={args.c} eps={args.eps} "
+         f"integrator={args.integrator or 'rk4'} t: {t0} -> {args.t_end}")
     rec = run(P, V, Mm, G=1.0, c=args.c, eps=args.eps, dt=dt, t_end=args.t_end,
               every=args.every, precision=args.precision, out_path=args.out, t0=t0, step0=step0,
               E_ref=E_ref, close=args.close, checkpoint=args.checkpoint,
-              meta={"model": args.model, "n_stars": args.n_stars, "seed": args.seed})
+              meta={"model": args.model, "n_stars": args.n_stars, "seed": args.seed},
+              integrator=args.integrator or "rk4")
     print(json.dumps(rec), flush=True)
 
 
