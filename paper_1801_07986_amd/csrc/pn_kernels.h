@@ -27,6 +27,14 @@
 // The star-star 1PN sum of Eq. (6) needs no pass-1 result of any other star
 // (only x, v, m and the O(N) massive-object terms u_j, b_j), so the potential
 // sweep and the 1PN sweep share one pass over j.
+//
+// The same four kernels instantiated on dual numbers (T = S = Dual) give the
+// time derivative of the force along the motion (the jerk of the Hermite
+// scheme), and their epilogue carries the Hermite corrector and predictor the
+// way the FP64 one carries the Runge-Kutta stage update.  Further down:
+// Eqs. (7)-(8) diagnostics (k_diag_*), close-encounter search (k_enc_*),
+// the unrestricted EIH equations (k_eih_*, reusing k_pair), and batched
+// ensembles (k_*_batched: one launch per phase for many systems).
 #pragma once
 
 #include <hip/hip_runtime.h>
