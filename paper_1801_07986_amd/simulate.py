@@ -107,7 +107,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--bh-mass", type=float, default=None,
                     help="plummer: black-hole mass (cold: 100 m, as in the paper)")
-    ap.add_argument("--c", type=float, default=1.0)
+    ap.add_argument("--c", type=float, default=None,
+                    help="speed of light (default 1; on --resume, the checkpoint's unless given: "
+                         "a different c restarts the energy reference at the resumed state)")
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--dt-log2", type=float, default=-15.0)
     ap.add_argument("--t-end", type=float, default=1.0)
@@ -130,14 +132,21 @@ def main(argv=None):
     if args.resume:
         pos, vel, mass, meta = load_checkpoint(args.resume)
         t0, step0, E_ref = meta["t"], meta["step"], meta["E_ref"]
-        args.c, args.eps, dt = meta["c"], meta["eps"], meta["dt"]
+        args.eps, dt = meta["eps"], meta["dt"]
+        if args.c is None or args.c == meta["c"]:
+            args.c = meta["c"]
+        else:
+            E_ref = None
+            _log(f"c = {args.c} instead of the checkpoint's {meta['c']}: energy reference restarts")
         if args.integrator is None:
             args.integrator = meta.get("integrator", "rk4")
         _log(f"resuming from t={t0} (step {step0})")
-    elif args.model == "cold":
-        pos, vel, mass = inputs.cold_sphere_bh(args.n_stars, args.seed)
     else:
-        pos, vel, mass = inputs.plummer_bh(args.n_stars + 1, args.bh_mass or 0.1, args.seed)
+        args.c = 1.0 if args.c is None else args.c
+        if args.model == "cold":
+            pos, vel, mass = inputs.cold_sphere_bh(args.n_stars, args.seed)
+        else:
+            pos, vel, mass = inputs.plummer_bh(args.n_stars + 1, args.bh_mass or 0.1, args.seed)
     dev = torch.device("cuda:0")
     P = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
     V = torch.from_numpy(np.ascontiguousarray(vel)).to(dev)
