@@ -93,7 +93,7 @@ Shape pick_shape(int Ns, int precision) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t pk, ub, bpart, part, bhpart, status, xs, vs, kx, kv, dpart, out8, ha, hj, xp, vp, ap,
+  size_t pk, ub, bpart, ub2, bpart2, part, bhpart, status, xs, vs, kx, kv, dpart, out8, ha, hj, xp, vp, ap,
       total;
 };
 
@@ -116,9 +116,16 @@ Layout layout_for(int64_t N, const Shape& s, Need need) {
     o += align256(bytes);
     return at;
   };
+  // massive-object block rows: one per 64 stars (kProRows per prologue
+  // workgroup, one per epilogue workgroup).  Runge-Kutta steps chain their
+  // evaluations: each stage's epilogue writes the next stage's u/b rows and
+  // block rows into the other of two buffers.
+  const size_t nrows = nb * kProRows;
   L.pk = take(Ns * (dual ? sizeof(PkDual) : sizeof(PkF64)));
   L.ub = take(Ns * 4 * W * sizeof(double));
-  L.bpart = take(nb * 8 * W * sizeof(double));
+  L.bpart = take(nrows * 8 * W * sizeof(double));
+  L.ub2 = take(rk4 ? Ns * 4 * sizeof(double) : 0);
+  L.bpart2 = take(rk4 ? nrows * 8 * sizeof(double) : 0);
   L.part = take((size_t)s.nsplit * std::max<size_t>(kNF * W, kND) * Ns * sizeof(double));
   L.bhpart = take(((Ns + kEpiStars - 1) / kEpiStars) * 4 * W * sizeof(double));
   L.status = take(sizeof(int));
@@ -382,12 +389,16 @@ struct Outs {
   double* jerk = nullptr;
   int herm = -1;
   double *HA = nullptr, *HJ = nullptr, *XP = nullptr, *VP = nullptr;
+  // chained Runge-Kutta stage: reads u/b and block rows from buffer `chain`
+  // (0 or 1), writes the next stage's packets (of `precision`) and rows into
+  // the other; -1: not chained
+  int chain = -1;
+  int precision = PN_FP64;
 };
 
 int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o, hipStream_t st) {
   const int Ns = (int)(s.N - 1);
-  const int nb = (Ns + kBlock - 1) / kBlock;            // prologue workgroups
-  const int ne = (Ns + kEpiStars - 1) / kEpiStars;      // epilogue workgroups
+  const int ne = (Ns + kEpiStars - 1) / kEpiStars;  // epilogue workgroups = prologue rows
   EpiArgs a;
   a.pos = s.pos;
   a.vel = s.vel;
@@ -398,7 +409,7 @@ int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o,
   a.eps2 = s.eps * s.eps;
   a.ub = P.at<double>(P.L.ub);
   a.bpart = P.at<double>(P.L.bpart);
-  a.nbpro = nb;
+  a.nbpro = ne;
   a.part = P.at<double>(P.L.part);
   a.nsplit = sh.nsplit;
   a.newton_only = o.newton_only ? 1 : 0;
@@ -427,7 +438,22 @@ int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o,
   a.HJ = o.HJ;
   a.XP = o.XP;
   a.VP = o.VP;
-  if (o.dual) {
+  if (o.chain >= 0) {
+    double* ubs[2] = {P.at<double>(P.L.ub), P.at<double>(P.L.ub2)};
+    double* bps[2] = {P.at<double>(P.L.bpart), P.at<double>(P.L.bpart2)};
+    a.ub = ubs[o.chain];
+    a.bpart = bps[o.chain];
+    a.nbpro = ne;
+    a.pk_next = P.at<void>(P.L.pk);
+    a.ub_next = ubs[1 - o.chain];
+    a.bpart_next = bps[1 - o.chain];
+    if (o.precision == PN_MIXED)
+      hipLaunchKernelGGL(k_epilogue_chain<float>, dim3(ne), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_epilogue_chain<double>, dim3(ne), dim3(kBlock), 0, st, a);
+    HIPCK(hipGetLastError());
+    hipLaunchKernelGGL(k_bh_final<double>, dim3(1), dim3(kBlock), 0, st, a);
+  } else if (o.dual) {
     hipLaunchKernelGGL(k_epilogue<Dual>, dim3(ne), dim3(kBlock), 0, st, a);
     HIPCK(hipGetLastError());
     hipLaunchKernelGGL(k_bh_final<Dual>, dim3(1), dim3(kBlock), 0, st, a);
@@ -477,17 +503,22 @@ struct Timer {
   }
 };
 
-// One force evaluation (+ optional RK4 stage update).
+// One force evaluation (+ optional RK4 stage update).  A chained stage
+// (o.chain >= 0) finds its packets already written by the previous epilogue.
 int enqueue_eval(const Sys& s, const Ptrs& P, const Shape& sh, int precision, const Outs& o,
                  hipStream_t st, Timer* tm) {
   int rc;
-  if ((rc = launch_prologue(s, P, precision, st))) return rc;
+  if (o.chain < 0 && (rc = launch_prologue(s, P, precision, st))) return rc;
   if (tm && (rc = tm->begin(st))) return rc;
   if ((rc = launch_pair(s, P, sh, precision, MODE_FUSED, st))) return rc;
   if (tm && (rc = tm->end(st))) return rc;
   return launch_epilogue(s, P, sh, o, st);
 }
 
+// One RK4 step of four chained evaluations: stage k reads the u/b and block
+// rows of buffer k % 2 and writes the next stage's into the other (stage 3:
+// the next step's stage 0, buffer 0 again).  The packets and buffer 0 of the
+// first stage come from a prologue launched before the first step.
 int enqueue_rk4_step(const Sys& s, const Ptrs& P, const Shape& sh, int precision, double dt,
                      double* X, double* V, hipStream_t st, Timer* tm) {
   double* Xs = P.at<double>(P.L.xs);
@@ -505,6 +536,8 @@ int enqueue_rk4_step(const Sys& s, const Ptrs& P, const Shape& sh, int precision
     o.Vs = Vs;
     o.KX = P.at<double>(P.L.kx);
     o.KV = P.at<double>(P.L.kv);
+    o.chain = stage & 1;
+    o.precision = precision;
     int rc = enqueue_eval(e, P, sh, precision, o, st, tm);
     if (rc) return rc;
   }
@@ -705,7 +738,7 @@ BatchPlan plan_batch(int n_sys, const int64_t* off, const double* G, const doubl
   P.o_pre_epi = take((n_sys + 1) * sizeof(int));
   P.o_pk = take((size_t)star0 * sizeof(PkF64));
   P.o_ub = take((size_t)star0 * 4 * sizeof(double));
-  P.o_bpart = take((size_t)pro0 * 8 * sizeof(double));
+  P.o_bpart = take((size_t)pro0 * kProRows * 8 * sizeof(double));
   P.o_part = take((size_t)part0 * sizeof(double));
   P.o_bhpart = take((size_t)epi0 * 4 * sizeof(double));
   P.o_status = take(sizeof(int));
@@ -933,6 +966,7 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
   const bool timing = (flags & PN_TIMING) != 0;
   const bool graph = !(flags & (PN_NOGRAPH | PN_TIMING));
   if (nsteps > 0) {
+    if ((rc = launch_prologue(s, P, precision, st))) return rc;  // stage 0's packets, buffer 0
     if (!graph) {
       Timer tm;
       tm.d = d;

@@ -39,11 +39,13 @@
 
 #include <hip/hip_runtime.h>
 #include <climits>
+#include <type_traits>
 #include <stdint.h>
 
 namespace pn {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+constexpr int kProRows = kBlock / 64;  // prologue block rows per workgroup (one per 64 stars)
 constexpr int kNF = 11;      // pair-sum fields: U, G(3), Q(3), C2, Q7(3)
 enum Field { F_U = 0, F_G = 1, F_Q = 4, F_C2 = 7, F_Q7 = 8 };
 enum PairMode { MODE_P1 = 1, MODE_P2 = 2, MODE_FUSED = 3 };
@@ -203,6 +205,26 @@ __device__ __forceinline__ void block_sum(const double (&v)[K], double* lds) {
   }
 }
 
+// Per-wavefront sums of K doubles per thread (64 values each, tree order);
+// the sum of wavefront w in lds[k*kBlock + 64 w].  The prologue (a row per
+// wavefront) and the epilogue (its stars in wavefront 0) reduce their
+// massive-object rows this way, so that a row holds the same sum whichever
+// kernel wrote it.
+template <int K>
+__device__ __forceinline__ void wave_sums(const double (&v)[K], double* lds) {
+  const int t = threadIdx.x, l = t & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) lds[k * kBlock + t] = v[k];
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if (l < s) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) lds[k * kBlock + t] += lds[k * kBlock + t + s];
+    }
+    __syncthreads();
+  }
+}
+
 // Wave index as a scalar (so that loop bounds derived from it stay uniform
 // and j packets keep coming through scalar loads).
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -240,13 +262,58 @@ struct ProArgs {
   double G, eps2;
   void* pk;       // [Ns] packets (PkOf<T>)
   double* ub;     // [Ns][4 W]: u_s, b_s(3)
-  double* bpart;  // [gridDim.x][8 W]: sum m b (3), sum m u, sum m v (3), 0
+  double* bpart;  // [gridDim.x * kProRows][8 W]: per 64 stars sum m b (3), sum m u, sum m v (3), 0
   int* status;
   // jerk sweep (T = Dual): time derivatives of pos and vel (the velocity and
   // the acceleration of the evaluation state)
   const double* pos_d = nullptr;
   const double* vel_d = nullptr;
 };
+
+// Prologue terms of star k (body k + 1) at position xs, velocity vs, with the
+// massive object at x0: writes the packet pk[k] and the row ub[k] = (u, b),
+// and returns the star's block-sum terms v = (m b, m u, m v).  Shared by the
+// prologue and by the Runge-Kutta epilogue that prepares the next evaluation.
+template <typename T, typename S>
+__device__ __forceinline__ void star_terms(const S (&x0)[3], const S (&xs)[3], const S (&vs)[3],
+                                           double m, double G, double gM, double eps2, void* pk,
+                                           double* ub_rows, int k, S (&v)[7]) {
+  constexpr int W = Width<T>::n;
+  const S dx = xs[0] - x0[0], dy = xs[1] - x0[1], dz = xs[2] - x0[2];
+  const S rinv = rsqrt_t(fma(dz, dz, fma(dy, dy, fma(dx, dx, S(eps2)))));
+  const S u = gM * rinv;
+  const S b3 = u * rinv * rinv;
+  const S bx = b3 * dx, by = b3 * dy, bz = b3 * dz;
+  const S vx = vs[0], vy = vs[1], vz = vs[2];
+  const S v2 = fma(vz, vz, fma(vy, vy, vx * vx));
+  using Pk = typename PkOf<T>::type;
+  Pk p;
+  p.x = xs[0];
+  p.y = xs[1];
+  p.z = xs[2];
+  p.gm = (T)(G * m);
+  p.svx = (T)(kSqrt32 * vx);
+  p.svy = (T)(kSqrt32 * vy);
+  p.svz = (T)(kSqrt32 * vz);
+  p.e = (T)fma(S(-2.0), v2, u);
+  p.hbx = (T)(-0.5 * bx);
+  p.hby = (T)(-0.5 * by);
+  p.hbz = (T)(-0.5 * bz);
+  clear_pad(p);
+  static_cast<Pk*>(pk)[k] = p;
+  double* ub = ub_rows + 4 * W * (size_t)k;
+  put(ub, 0, 4, u);
+  put(ub, 1, 4, bx);
+  put(ub, 2, 4, by);
+  put(ub, 3, 4, bz);
+  v[0] = m * bx;
+  v[1] = m * by;
+  v[2] = m * bz;
+  v[3] = m * u;
+  v[4] = m * vx;
+  v[5] = m * vy;
+  v[6] = m * vz;
+}
 
 // W = Width<T>::n doubles per quantity (value, and derivative for Dual).
 template <typename T>
@@ -257,60 +324,28 @@ __device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double
   S v[7] = {0, 0, 0, 0, 0, 0, 0};
   if (k < a.Ns) {
     const int s = k + 1;
-    const S x0 = ld<S>(a.pos, a.pos_d, 0), y0 = ld<S>(a.pos, a.pos_d, 1),
-            z0 = ld<S>(a.pos, a.pos_d, 2);
-    const S xs = ld<S>(a.pos, a.pos_d, 3 * s), ys = ld<S>(a.pos, a.pos_d, 3 * s + 1),
-            zs = ld<S>(a.pos, a.pos_d, 3 * s + 2);
-    const S dx = xs - x0, dy = ys - y0, dz = zs - z0;
-    const S rinv = rsqrt_t(fma(dz, dz, fma(dy, dy, fma(dx, dx, S(a.eps2)))));
-    const double gM = a.G * a.mass[0];
-    const S u = gM * rinv;
-    const S b3 = u * rinv * rinv;
-    const S bx = b3 * dx, by = b3 * dy, bz = b3 * dz;
-    S vx = 0.0, vy = 0.0, vz = 0.0;
+    const S x0[3] = {ld<S>(a.pos, a.pos_d, 0), ld<S>(a.pos, a.pos_d, 1),
+                     ld<S>(a.pos, a.pos_d, 2)};
+    const S xs[3] = {ld<S>(a.pos, a.pos_d, 3 * s), ld<S>(a.pos, a.pos_d, 3 * s + 1),
+                     ld<S>(a.pos, a.pos_d, 3 * s + 2)};
+    S vs[3] = {0.0, 0.0, 0.0};
     if (a.vel) {
-      vx = ld<S>(a.vel, a.vel_d, 3 * s);
-      vy = ld<S>(a.vel, a.vel_d, 3 * s + 1);
-      vz = ld<S>(a.vel, a.vel_d, 3 * s + 2);
+      vs[0] = ld<S>(a.vel, a.vel_d, 3 * s);
+      vs[1] = ld<S>(a.vel, a.vel_d, 3 * s + 1);
+      vs[2] = ld<S>(a.vel, a.vel_d, 3 * s + 2);
     }
-    const S v2 = fma(vz, vz, fma(vy, vy, vx * vx));
-    const double m = a.mass[s];
-    using Pk = typename PkOf<T>::type;
-    Pk p;
-    p.x = xs;
-    p.y = ys;
-    p.z = zs;
-    p.gm = (T)(a.G * m);
-    p.svx = (T)(kSqrt32 * vx);
-    p.svy = (T)(kSqrt32 * vy);
-    p.svz = (T)(kSqrt32 * vz);
-    p.e = (T)fma(S(-2.0), v2, u);
-    p.hbx = (T)(-0.5 * bx);
-    p.hby = (T)(-0.5 * by);
-    p.hbz = (T)(-0.5 * bz);
-    clear_pad(p);
-    static_cast<Pk*>(a.pk)[k] = p;
-    double* ub = a.ub + 4 * W * (size_t)k;
-    put(ub, 0, 4, u);
-    put(ub, 1, 4, bx);
-    put(ub, 2, 4, by);
-    put(ub, 3, 4, bz);
-    v[0] = m * bx;
-    v[1] = m * by;
-    v[2] = m * bz;
-    v[3] = m * u;
-    v[4] = m * vx;
-    v[5] = m * vy;
-    v[6] = m * vz;
+    star_terms<T, S>(x0, xs, vs, a.mass[s], a.G, a.G * a.mass[0], a.eps2, a.pk, a.ub, k, v);
   }
   double flat[7 * W];
 #pragma unroll
   for (int q = 0; q < 7; ++q) put(flat, q, 7, v[q]);
-  block_sum<7 * W>(flat, lds);
-  if (threadIdx.x < 8 * W) {
+  wave_sums<7 * W>(flat, lds);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l < 8 * W) {
     // row layout: value columns 0..7, derivative columns 8..15 (Dual)
-    const int q = threadIdx.x & 7, h = threadIdx.x >> 3;
-    a.bpart[(size_t)blk * 8 * W + threadIdx.x] = q < 7 ? lds[(h * 7 + q) * kBlock] : 0.0;
+    const int q = l & 7, h = l >> 3;
+    a.bpart[((size_t)blk * kProRows + w) * 8 * W + l] =
+        q < 7 ? lds[(h * 7 + q) * kBlock + 64 * w] : 0.0;
   }
   if (blk == 0 && threadIdx.x == 0) {
     const double M = a.mass[0];
@@ -619,38 +654,49 @@ struct EpiArgs {
   // next predicted state, all [N][3]
   int herm = -1;
   double *HA = nullptr, *HJ = nullptr, *XP = nullptr, *VP = nullptr;
+  // chained Runge-Kutta stages (k_epilogue_chain): the next evaluation's
+  // packets, u/b rows and block-sum rows (one per epilogue workgroup)
+  void* pk_next = nullptr;
+  double* ub_next = nullptr;
+  double* bpart_next = nullptr;
 };
 
 // Classical RK4 bookkeeping for one body component.  The evaluation state of
 // stage 0 is (X, V); of stages 1-3 it is (Xs, Vs).  KX/KV accumulate
 // k1 + 2 k2 + 2 k3; stage 3 applies y += dt/6 (k1 + 2 k2 + 2 k3 + k4).
-__device__ __forceinline__ void rk4_update(const EpiArgs& a, size_t o, double xv, double acc) {
-  // xv: velocity of the evaluation state (the position derivative k_x)
-  switch (a.stage) {
+// rk4_next gives the component of the next evaluation state (stage 3: the new
+// step's state) from the stage derivative k and the step-start value Y; the
+// same function serves position and velocity, and the epilogue uses it for
+// the massive object's next position too, so that every thread derives that
+// position bit for bit as k_bh_final does.
+__device__ __forceinline__ double rk4_next(int stage, double dt, double Y, double K, double k) {
+  switch (stage) {
     case 0:
-      a.KX[o] = xv;
-      a.KV[o] = acc;
-      a.Xs[o] = a.X[o] + 0.5 * a.dt * xv;
-      a.Vs[o] = a.V[o] + 0.5 * a.dt * acc;
-      break;
     case 1:
-      a.KX[o] = a.KX[o] + 2.0 * xv;
-      a.KV[o] = a.KV[o] + 2.0 * acc;
-      a.Xs[o] = a.X[o] + 0.5 * a.dt * xv;
-      a.Vs[o] = a.V[o] + 0.5 * a.dt * acc;
-      break;
+      return Y + 0.5 * dt * k;
     case 2:
-      a.KX[o] = a.KX[o] + 2.0 * xv;
-      a.KV[o] = a.KV[o] + 2.0 * acc;
-      a.Xs[o] = a.X[o] + a.dt * xv;
-      a.Vs[o] = a.V[o] + a.dt * acc;
-      break;
-    case 3:
-      a.X[o] = a.X[o] + a.dt / 6.0 * (a.KX[o] + xv);
-      a.V[o] = a.V[o] + a.dt / 6.0 * (a.KV[o] + acc);
-      break;
+      return Y + dt * k;
     default:
-      break;
+      return Y + dt / 6.0 * (K + k);
+  }
+}
+// xv: velocity of the evaluation state (the position derivative k_x); returns
+// the next evaluation state's position and velocity component in xn, vn.
+__device__ __forceinline__ void rk4_update(const EpiArgs& a, size_t o, double xv, double acc,
+                                           double& xn, double& vn) {
+  if (a.stage < 0 || a.stage > 3) return;
+  const double KX = a.stage == 0 ? 0.0 : a.KX[o];
+  const double KV = a.stage == 0 ? 0.0 : a.KV[o];
+  xn = rk4_next(a.stage, a.dt, a.X[o], KX, xv);
+  vn = rk4_next(a.stage, a.dt, a.V[o], KV, acc);
+  if (a.stage < 3) {
+    a.KX[o] = a.stage == 0 ? xv : KX + 2.0 * xv;
+    a.KV[o] = a.stage == 0 ? acc : KV + 2.0 * acc;
+    a.Xs[o] = xn;
+    a.Vs[o] = vn;
+  } else {
+    a.X[o] = xn;
+    a.V[o] = vn;
   }
 }
 
@@ -723,8 +769,11 @@ __device__ __forceinline__ bool epi_field_used(int f, const EpiArgs& a) {
 }
 
 // S = double: the evaluation; S = Dual: the same arithmetic on dual numbers
-// (acceleration and jerk).
-template <typename S>
+// (acceleration and jerk).  PkT (S = double, Runge-Kutta stages only): also
+// the next evaluation's prologue, from each star's next state and the massive
+// object's next position, into pk_next, ub_next and bpart_next (packets of
+// PkOf<PkT>); void: none.
+template <typename S, typename PkT = void>
 __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double* lds,
                                                double* fsum) {
   constexpr bool DUAL = IsDual<S>::value;
@@ -774,8 +823,11 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   }
   __syncthreads();
 
+  constexpr bool CHAIN = !std::is_void<PkT>::value;
+  static_assert(!CHAIN || !DUAL, "chained stages are FP64 evaluations");
   const int k = blk * kEpiStars + threadIdx.x;
   S bh[3] = {0.0, 0.0, 0.0};
+  double pro[7] = {0, 0, 0, 0, 0, 0, 0};
   if (threadIdx.x < kEpiStars && k < a.Ns) {
     const int i = k + 1;
     const int t = threadIdx.x;
@@ -871,18 +923,39 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
       }
     } else {
       if (a.stage >= 0) {
-        for (int c = 0; c < 3; ++c) rk4_update(a, 3 * (size_t)i + c, vi[c], at[c]);
+        double xn[3] = {0.0, 0.0, 0.0}, vn[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; ++c) rk4_update(a, 3 * (size_t)i + c, vi[c], at[c], xn[c], vn[c]);
+        if constexpr (CHAIN) {
+          // the massive object's next position, as k_bh_final will compute it
+          double x0n[3];
+          for (int c = 0; c < 3; ++c)
+            x0n[c] = rk4_next(a.stage, a.dt, a.X[c], a.stage == 0 ? 0.0 : a.KX[c], a.vel[c]);
+          star_terms<PkT, double>(x0n, xn, vn, a.mass[i], a.G, gM, a.eps2, a.pk_next, a.ub_next,
+                                  k, pro);
+        }
       }
     }
   }
-  double bhs[3 * W];
+  constexpr int NB = CHAIN ? 3 + 7 : 3 * W;
+  double bhs[NB];
 #pragma unroll
   for (int c = 0; c < 3; ++c) put(bhs, c, 3, bh[c]);
-  block_sum<3 * W>(bhs, lds);
+  if constexpr (CHAIN) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) bhs[3 + q] = pro[q];
+  }
+  wave_sums<NB>(bhs, lds);  // the stars are in wavefront 0
   if (threadIdx.x < 4 * W) {
     // row layout: values in columns 0..2, derivatives in 4..6 (Dual)
     const int q = threadIdx.x & 3, h = threadIdx.x >> 2;
     a.bhpart[(size_t)blk * 4 * W + threadIdx.x] = q < 3 ? lds[(h * 3 + q) * kBlock] : 0.0;
+  }
+  if constexpr (CHAIN) {
+    // the prologue's row layout: sum m b (3), sum m u, sum m v (3), 0
+    if (threadIdx.x >= 64 && threadIdx.x < 72) {
+      const int q = threadIdx.x - 64;
+      a.bpart_next[(size_t)blk * 8 + q] = q < 7 ? lds[(3 + q) * kBlock] : 0.0;
+    }
   }
 }
 
@@ -891,6 +964,15 @@ __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   __shared__ double lds[(IsDual<S>::value ? 16 : 7) * kBlock];
   __shared__ double fsum[kNF * Width<S>::n * kEpiStars];
   epilogue_block<S>(a, blockIdx.x, lds, fsum);
+}
+
+// Runge-Kutta stage epilogue that also performs the next evaluation's
+// prologue (packets of PkOf<T>), saving that kernel's launch.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_epilogue_chain(EpiArgs a) {
+  __shared__ double lds[10 * kBlock];
+  __shared__ double fsum[kNF * kEpiStars];
+  epilogue_block<double, T>(a, blockIdx.x, lds, fsum);
 }
 
 template <typename S>
@@ -940,7 +1022,8 @@ __device__ __forceinline__ void bh_final_block(const EpiArgs& a, double* lds) {
       }
     } else {
       if (a.stage >= 0) {
-        for (int c = 0; c < 3; ++c) rk4_update(a, (size_t)c, v0[c], at[c]);
+        double xn, vn;
+        for (int c = 0; c < 3; ++c) rk4_update(a, (size_t)c, v0[c], at[c], xn, vn);
       }
     }
   }
@@ -1450,7 +1533,7 @@ __device__ __forceinline__ ProArgs batch_pro_args(const BatchArgs& b, const SysD
   a.eps2 = S.eps2;
   a.pk = static_cast<Pk*>(b.pk) + S.star0;
   a.ub = b.ub + 4 * S.star0;
-  a.bpart = b.bpart + 8 * (int64_t)S.pro0;
+  a.bpart = b.bpart + 8 * kProRows * (int64_t)S.pro0;
   a.status = b.status;
   return a;
 }
@@ -1466,8 +1549,8 @@ __device__ __forceinline__ EpiArgs batch_epi_args(const BatchArgs& b, const SysD
   a.lam = S.lam;
   a.eps2 = S.eps2;
   a.ub = b.ub + 4 * S.star0;
-  a.bpart = b.bpart + 8 * (int64_t)S.pro0;
-  a.nbpro = S.npro;
+  a.bpart = b.bpart + 8 * kProRows * (int64_t)S.pro0;
+  a.nbpro = S.nepi;  // one prologue row per 64 stars
   a.part = b.part + S.part0;
   a.nsplit = S.nsplit;
   a.newton_only = 0;
