@@ -396,7 +396,7 @@ struct Outs {
   int precision = PN_FP64;
 };
 
-int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o, hipStream_t st) {
+EpiArgs epi_args(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o) {
   const int Ns = (int)(s.N - 1);
   const int ne = (Ns + kEpiStars - 1) / kEpiStars;  // epilogue workgroups = prologue rows
   EpiArgs a;
@@ -443,16 +443,25 @@ int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o,
     double* bps[2] = {P.at<double>(P.L.bpart), P.at<double>(P.L.bpart2)};
     a.ub = ubs[o.chain];
     a.bpart = bps[o.chain];
-    a.nbpro = ne;
     a.pk_next = P.at<void>(P.L.pk);
     a.ub_next = ubs[1 - o.chain];
     a.bpart_next = bps[1 - o.chain];
+  }
+  return a;
+}
+
+// Epilogue and massive-object update of one evaluation.  A chained stage
+// (o.chain >= 0) launches the epilogue only: its massive-object update rides
+// on the next stage's sweep (launch_pair_bh) or follows alone (launch_bh_final).
+int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o, hipStream_t st) {
+  const int Ns = (int)(s.N - 1);
+  const int ne = (Ns + kEpiStars - 1) / kEpiStars;
+  const EpiArgs a = epi_args(s, P, sh, o);
+  if (o.chain >= 0) {
     if (o.precision == PN_MIXED)
       hipLaunchKernelGGL(k_epilogue_chain<float>, dim3(ne), dim3(kBlock), 0, st, a);
     else
       hipLaunchKernelGGL(k_epilogue_chain<double>, dim3(ne), dim3(kBlock), 0, st, a);
-    HIPCK(hipGetLastError());
-    hipLaunchKernelGGL(k_bh_final<double>, dim3(1), dim3(kBlock), 0, st, a);
   } else if (o.dual) {
     hipLaunchKernelGGL(k_epilogue<Dual>, dim3(ne), dim3(kBlock), 0, st, a);
     HIPCK(hipGetLastError());
@@ -462,6 +471,44 @@ int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o,
     HIPCK(hipGetLastError());
     hipLaunchKernelGGL(k_bh_final<double>, dim3(1), dim3(kBlock), 0, st, a);
   }
+  HIPCK(hipGetLastError());
+  return PN_OK;
+}
+
+int launch_bh_final(const EpiArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_bh_final<double>, dim3(1), dim3(kBlock), 0, st, a);
+  HIPCK(hipGetLastError());
+  return PN_OK;
+}
+
+template <typename T>
+void launch_pair_bh_t(const PairArgs& a, const EpiArgs& e, const Shape& sh, hipStream_t st) {
+  dim3 grid(sh.iblocks + 1, sh.nsplit);
+  if (sh.ws == 4) {
+    if (sh.ipt == 2)
+      hipLaunchKernelGGL((k_pair_bh<T, MODE_FUSED, 2, 4>), grid, dim3(kBlock), 0, st, a, e);
+    else
+      hipLaunchKernelGGL((k_pair_bh<T, MODE_FUSED, 1, 4>), grid, dim3(kBlock), 0, st, a, e);
+  } else {
+    if (sh.ipt == 2)
+      hipLaunchKernelGGL((k_pair_bh<T, MODE_FUSED, 2, 1>), grid, dim3(kBlock), 0, st, a, e);
+    else
+      hipLaunchKernelGGL((k_pair_bh<T, MODE_FUSED, 1, 1>), grid, dim3(kBlock), 0, st, a, e);
+  }
+}
+
+// The fused sweep of the state s with, in one extra workgroup, the
+// massive-object update e of the previous chained stage.
+int launch_pair_bh(const Sys& s, const Ptrs& P, const Shape& sh, int precision, const EpiArgs& e,
+                   hipStream_t st) {
+  PairArgs a;
+  a.pk = P.at<void>(P.L.pk);
+  a.Ns = (int)(s.N - 1);
+  a.jchunk = sh.jchunk;
+  a.eps2 = s.eps * s.eps;
+  a.part = P.at<double>(P.L.part);
+  if (precision == PN_MIXED) launch_pair_bh_t<float>(a, e, sh, st);
+  else launch_pair_bh_t<double>(a, e, sh, st);
   HIPCK(hipGetLastError());
   return PN_OK;
 }
@@ -503,43 +550,74 @@ struct Timer {
   }
 };
 
-// One force evaluation (+ optional RK4 stage update).  A chained stage
-// (o.chain >= 0) finds its packets already written by the previous epilogue.
+// One force evaluation (+ optional RK4 stage update).
 int enqueue_eval(const Sys& s, const Ptrs& P, const Shape& sh, int precision, const Outs& o,
                  hipStream_t st, Timer* tm) {
   int rc;
-  if (o.chain < 0 && (rc = launch_prologue(s, P, precision, st))) return rc;
+  if ((rc = launch_prologue(s, P, precision, st))) return rc;
   if (tm && (rc = tm->begin(st))) return rc;
   if ((rc = launch_pair(s, P, sh, precision, MODE_FUSED, st))) return rc;
   if (tm && (rc = tm->end(st))) return rc;
   return launch_epilogue(s, P, sh, o, st);
 }
 
-// One RK4 step of four chained evaluations: stage k reads the u/b and block
-// rows of buffer k % 2 and writes the next stage's into the other (stage 3:
-// the next step's stage 0, buffer 0 again).  The packets and buffer 0 of the
-// first stage come from a prologue launched before the first step.
-int enqueue_rk4_step(const Sys& s, const Ptrs& P, const Shape& sh, int precision, double dt,
-                     double* X, double* V, hipStream_t st, Timer* tm) {
+// Chained RK4 steps.  Stage k of a step evaluates at (X, V) (k = 0) or
+// (Xs, Vs); its epilogue (k_epilogue_chain) reads the u/b and block rows of
+// buffer k % 2 and writes the next stage's packets and rows (stage 3: the next
+// step's stage 0, buffer 0 again) into the other; its massive-object update
+// runs in an extra workgroup of the next stage's sweep (k_pair_bh).  So a run
+// of steps is: prologue at (X, V), the first sweep (enqueue_rk4_head), then
+// per step enqueue_rk4_body, whose last update rides on the next step's first
+// sweep (more) or runs alone after the last step.
+void rk4_stage(const Sys& s, const Ptrs& P, int precision, double dt, double* X, double* V,
+               int stage, Sys& e, Outs& o) {
   double* Xs = P.at<double>(P.L.xs);
   double* Vs = P.at<double>(P.L.vs);
+  e = s;
+  e.pos = stage == 0 ? X : Xs;
+  e.vel = stage == 0 ? V : Vs;
+  o = Outs();
+  o.stage = stage;
+  o.dt = dt;
+  o.X = X;
+  o.V = V;
+  o.Xs = Xs;
+  o.Vs = Vs;
+  o.KX = P.at<double>(P.L.kx);
+  o.KV = P.at<double>(P.L.kv);
+  o.chain = stage & 1;
+  o.precision = precision;
+}
+
+int enqueue_rk4_head(const Sys& s, const Ptrs& P, const Shape& sh, int precision, double dt,
+                     double* X, double* V, hipStream_t st, Timer* tm) {
+  Sys e;
+  Outs o;
+  rk4_stage(s, P, precision, dt, X, V, 0, e, o);
+  int rc;
+  if (tm && (rc = tm->begin(st))) return rc;
+  if ((rc = launch_pair(e, P, sh, precision, MODE_FUSED, st))) return rc;
+  if (tm && (rc = tm->end(st))) return rc;
+  return PN_OK;
+}
+
+int enqueue_rk4_body(const Sys& s, const Ptrs& P, const Shape& sh, int precision, double dt,
+                     double* X, double* V, bool more, hipStream_t st, Timer* tm) {
   for (int stage = 0; stage < 4; ++stage) {
-    Sys e = s;
-    e.pos = stage == 0 ? X : Xs;
-    e.vel = stage == 0 ? V : Vs;
-    Outs o;
-    o.stage = stage;
-    o.dt = dt;
-    o.X = X;
-    o.V = V;
-    o.Xs = Xs;
-    o.Vs = Vs;
-    o.KX = P.at<double>(P.L.kx);
-    o.KV = P.at<double>(P.L.kv);
-    o.chain = stage & 1;
-    o.precision = precision;
-    int rc = enqueue_eval(e, P, sh, precision, o, st, tm);
-    if (rc) return rc;
+    Sys e, en;
+    Outs o, on;
+    rk4_stage(s, P, precision, dt, X, V, stage, e, o);
+    int rc;
+    if ((rc = launch_epilogue(e, P, sh, o, st))) return rc;
+    const EpiArgs a = epi_args(e, P, sh, o);
+    if (stage < 3 || more) {
+      rk4_stage(s, P, precision, dt, X, V, (stage + 1) & 3, en, on);
+      if (tm && (rc = tm->begin(st))) return rc;
+      if ((rc = launch_pair_bh(en, P, sh, precision, a, st))) return rc;
+      if (tm && (rc = tm->end(st))) return rc;
+    } else if ((rc = launch_bh_final(a, st))) {
+      return rc;
+    }
   }
   return PN_OK;
 }
@@ -971,8 +1049,10 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
       Timer tm;
       tm.d = d;
       tm.on = timing;
+      if ((rc = enqueue_rk4_head(s, P, sh, precision, dt, pos, vel, st, &tm))) return rc;
       for (int64_t k = 0; k < nsteps; ++k)
-        if ((rc = enqueue_rk4_step(s, P, sh, precision, dt, pos, vel, st, &tm))) return rc;
+        if ((rc = enqueue_rk4_body(s, P, sh, precision, dt, pos, vel, k + 1 < nsteps, st, &tm)))
+          return rc;
       if ((rc = tm.collect((double)(N - 1) * (double)(N - 2)))) return rc;
     } else {
       GraphKey key;
@@ -989,10 +1069,17 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
       key.ws = sh.ws;
       key.nsplit = sh.nsplit;
       key.base = d->base;
-      rc = replay_step(*d, key, nsteps, st, [&](hipStream_t cs) {
-        return enqueue_rk4_step(s, P, sh, precision, dt, pos, vel, cs, nullptr);
-      });
-      if (rc) return rc;
+      // the first sweep, nsteps - 1 replayed steps (each ending in the next
+      // step's first sweep), and the last step launched directly
+      if ((rc = enqueue_rk4_head(s, P, sh, precision, dt, pos, vel, st, nullptr))) return rc;
+      if (nsteps > 1) {
+        rc = replay_step(*d, key, nsteps - 1, st, [&](hipStream_t cs) {
+          return enqueue_rk4_body(s, P, sh, precision, dt, pos, vel, true, cs, nullptr);
+        });
+        if (rc) return rc;
+      }
+      if ((rc = enqueue_rk4_body(s, P, sh, precision, dt, pos, vel, false, st, nullptr)))
+        return rc;
     }
   }
   return finish(*d, P, st, flags & ~PN_TIMING);

@@ -512,8 +512,15 @@ __device__ __forceinline__ bool field_written(int f, int mode) {
   return (mode & MODE_P2) != 0;
 }
 
+// LDS of pair_block's wavefront reduction: WS - 1 waves park their sums.
+template <typename T, int IPT, int WS>
+constexpr int pair_red_doubles() {
+  return WS > 1 ? (WS - 1) * kNF * Width<T>::n * IPT * 64 : 1;
+}
+
+// red: pair_red_doubles<T, IPT, WS>() doubles of LDS
 template <typename T, int MODE, int IPT, int WS>
-__device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
+__device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp, double* red) {
   using Pk = typename PkOf<T>::type;
   constexpr int NFO = kNF * Width<T>::n;  // output fields per star
   constexpr int LANES = kBlock / WS;  // distinct i-lanes per workgroup
@@ -583,7 +590,6 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
     // fixed-order reduction over the WS wavefronts: waves 1..WS-1 park their
     // sums in LDS, wave 0 adds them to its own in wave order and stores
     // (LDS of WS-1 waves only, so it does not cap the occupancy)
-    __shared__ double red[(WS - 1) * NFO * IPT * 64];
     if (wave > 0) {
 #pragma unroll
       for (int f = 0; f < NFO; ++f)
@@ -614,7 +620,8 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp) {
 
 template <typename T, int MODE, int IPT, int WS>
 __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
-  pair_block<T, MODE, IPT, WS>(a, blockIdx.x, blockIdx.y);
+  __shared__ double red[pair_red_doubles<T, IPT, WS>()];
+  pair_block<T, MODE, IPT, WS>(a, blockIdx.x, blockIdx.y, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1033,6 +1040,24 @@ template <typename S>
 __global__ __launch_bounds__(kBlock) void k_bh_final(EpiArgs a) {
   __shared__ double lds[(IsDual<S>::value ? 16 : 7) * kBlock];
   bh_final_block<S>(a, lds);
+}
+
+// The sweep of a chained Runge-Kutta stage with the previous stage's
+// massive-object update (k_bh_final's work) in one extra workgroup: the sweep
+// reads only star packets, which the previous epilogue has written, so the
+// two are independent and the stage saves a kernel boundary.  Grid: the
+// sweep's (iblocks + 1) x nsplit; column iblocks, split 0 runs the update
+// (sharing the sweep's LDS), the rest of that column exits.
+template <typename T, int MODE, int IPT, int WS>
+__global__ __launch_bounds__(kBlock) void k_pair_bh(PairArgs a, EpiArgs e) {
+  constexpr int L = pair_red_doubles<T, IPT, WS>() > 7 * kBlock ? pair_red_doubles<T, IPT, WS>()
+                                                                : 7 * kBlock;
+  __shared__ double lds[L];
+  if (blockIdx.x == gridDim.x - 1) {
+    if (blockIdx.y == 0) bh_final_block<double>(e, lds);
+    return;
+  }
+  pair_block<T, MODE, IPT, WS>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1593,7 +1618,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched(BatchArgs b) {
   a.jchunk = S.jchunk;
   a.eps2 = S.eps2;
   a.part = b.part + S.part0;
-  pair_block<T, MODE_FUSED, 1, 4>(a, local % S.iblocks, local / S.iblocks);
+  __shared__ double red[pair_red_doubles<T, 1, 4>()];
+  pair_block<T, MODE_FUSED, 1, 4>(a, local % S.iblocks, local / S.iblocks, red);
 }
 
 __global__ __launch_bounds__(kBlock) void k_epilogue_batched(BatchArgs b) {
