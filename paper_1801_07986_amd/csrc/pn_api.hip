@@ -93,7 +93,7 @@ Shape pick_shape(int Ns, int precision) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t pk, ub, bpart, ub2, bpart2, part, bhpart, status, xs, vs, kx, kv, dpart, out8, ha, hj, xp, vp, ap,
+  size_t pk, ub, bpart, ub2, bpart2, bhpart2, part, bhpart, status, xs, vs, kx, kv, dpart, out8, ha, hj, xp, vp, ap,
       total;
 };
 
@@ -119,15 +119,17 @@ Layout layout_for(int64_t N, const Shape& s, Need need) {
   // massive-object block rows: one per 64 stars (kProRows per prologue
   // workgroup, one per epilogue workgroup).  Runge-Kutta steps chain their
   // evaluations: each stage's epilogue writes the next stage's u/b rows and
-  // block rows into the other of two buffers.
+  // block rows into the other of two buffers; a jerk evaluation's FP64
+  // epilogue writes the jerk sweep's (dual) rows into the second buffers.
   const size_t nrows = nb * kProRows;
   L.pk = take(Ns * (dual ? sizeof(PkDual) : sizeof(PkF64)));
   L.ub = take(Ns * 4 * W * sizeof(double));
   L.bpart = take(nrows * 8 * W * sizeof(double));
-  L.ub2 = take(rk4 ? Ns * 4 * sizeof(double) : 0);
-  L.bpart2 = take(rk4 ? nrows * 8 * sizeof(double) : 0);
+  L.ub2 = take(rk4 || dual ? Ns * 4 * W * sizeof(double) : 0);
+  L.bpart2 = take(rk4 || dual ? nrows * 8 * W * sizeof(double) : 0);
   L.part = take((size_t)s.nsplit * std::max<size_t>(kNF * W, kND) * Ns * sizeof(double));
   L.bhpart = take(((Ns + kEpiStars - 1) / kEpiStars) * 4 * W * sizeof(double));
+  L.bhpart2 = take(dual ? ((Ns + kEpiStars - 1) / kEpiStars) * 4 * W * sizeof(double) : 0);
   L.status = take(sizeof(int));
   L.dpart = take(nb * 10 * sizeof(double));
   L.out8 = take(8 * sizeof(double));
@@ -394,6 +396,13 @@ struct Outs {
   // the other; -1: not chained
   int chain = -1;
   int precision = PN_FP64;
+  // jerk evaluation: the FP64 epilogue writes the jerk sweep's packets and
+  // (dual) rows into the second buffers (jerk_next), which the dual epilogue
+  // then reads, writing its own massive-object rows there too (second_rows);
+  // fp64_bh: the FP64 pass's massive-object update, run by the dual epilogue
+  bool jerk_next = false;
+  bool second_rows = false;
+  const EpiArgs* fp64_bh = nullptr;
 };
 
 EpiArgs epi_args(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o) {
@@ -447,21 +456,38 @@ EpiArgs epi_args(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o) {
     a.ub_next = ubs[1 - o.chain];
     a.bpart_next = bps[1 - o.chain];
   }
+  if (o.jerk_next) {
+    a.pk_next = P.at<void>(P.L.pk);
+    a.ub_next = P.at<double>(P.L.ub2);
+    a.bpart_next = P.at<double>(P.L.bpart2);
+  }
+  if (o.second_rows) {
+    a.ub = P.at<double>(P.L.ub2);
+    a.bpart = P.at<double>(P.L.bpart2);
+    a.bhpart = P.at<double>(P.L.bhpart2);
+  }
   return a;
 }
 
 // Epilogue and massive-object update of one evaluation.  A chained stage
-// (o.chain >= 0) launches the epilogue only: its massive-object update rides
-// on the next stage's sweep (launch_pair_bh) or follows alone (launch_bh_final).
+// (o.chain >= 0) or a jerk evaluation's FP64 pass (o.jerk_next) launches the
+// epilogue only: its massive-object update rides on the next sweep
+// (launch_pair_bh, launch_pair_dual) or follows alone (launch_bh_final).
 int launch_epilogue(const Sys& s, const Ptrs& P, const Shape& sh, const Outs& o, hipStream_t st) {
   const int Ns = (int)(s.N - 1);
   const int ne = (Ns + kEpiStars - 1) / kEpiStars;
   const EpiArgs a = epi_args(s, P, sh, o);
-  if (o.chain >= 0) {
+  if (o.jerk_next) {
+    hipLaunchKernelGGL(k_epilogue_chain<Dual>, dim3(ne), dim3(kBlock), 0, st, a);
+  } else if (o.chain >= 0) {
     if (o.precision == PN_MIXED)
       hipLaunchKernelGGL(k_epilogue_chain<float>, dim3(ne), dim3(kBlock), 0, st, a);
     else
       hipLaunchKernelGGL(k_epilogue_chain<double>, dim3(ne), dim3(kBlock), 0, st, a);
+  } else if (o.dual && o.fp64_bh) {
+    hipLaunchKernelGGL(k_epilogue_dual_bh, dim3(ne + 1), dim3(kBlock), 0, st, a, *o.fp64_bh);
+    HIPCK(hipGetLastError());
+    hipLaunchKernelGGL(k_bh_final<Dual>, dim3(1), dim3(kBlock), 0, st, a);
   } else if (o.dual) {
     hipLaunchKernelGGL(k_epilogue<Dual>, dim3(ne), dim3(kBlock), 0, st, a);
     HIPCK(hipGetLastError());
@@ -625,17 +651,26 @@ int enqueue_rk4_body(const Sys& s, const Ptrs& P, const Shape& sh, int precision
 // Acceleration and jerk at the state s: an FP64 evaluation writes the total
 // acceleration to acc, then the dual sweep differentiates the force along
 // (dx/dt, dv/dt) = (v, acc).  o carries the dual pass's outputs.
+// Six kernels: prologue, FP64 sweep, FP64 epilogue that also writes the jerk
+// sweep's packets and rows (second buffers), the jerk sweep, the dual
+// epilogue carrying the FP64 massive-object update, the dual massive-object
+// update.
 int enqueue_jerk(const Sys& s, const Ptrs& P, const Shape& sh, double* acc, Outs o,
                  hipStream_t st) {
   Outs e;
   e.acc_tot = acc;
-  int rc = enqueue_eval(s, P, sh, PN_FP64, e, st, nullptr);
-  if (rc) return rc;
-  if ((rc = launch_prologue(s, P, PN_FP64, st, true, s.vel, acc))) return rc;
+  e.jerk_next = true;
+  int rc;
+  if ((rc = launch_prologue(s, P, PN_FP64, st))) return rc;
+  if ((rc = launch_pair(s, P, sh, PN_FP64, MODE_FUSED, st))) return rc;
+  if ((rc = launch_epilogue(s, P, sh, e, st))) return rc;
   if ((rc = launch_pair_dual(s, P, sh, st))) return rc;
+  const EpiArgs fp64 = epi_args(s, P, sh, e);
   o.dual = true;
   o.pos_d = s.vel;
   o.vel_d = acc;
+  o.second_rows = true;
+  o.fp64_bh = &fp64;
   return launch_epilogue(s, P, sh, o, st);
 }
 

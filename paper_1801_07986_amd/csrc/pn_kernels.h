@@ -776,10 +776,12 @@ __device__ __forceinline__ bool epi_field_used(int f, const EpiArgs& a) {
 }
 
 // S = double: the evaluation; S = Dual: the same arithmetic on dual numbers
-// (acceleration and jerk).  PkT (S = double, Runge-Kutta stages only): also
-// the next evaluation's prologue, from each star's next state and the massive
-// object's next position, into pk_next, ub_next and bpart_next (packets of
-// PkOf<PkT>); void: none.
+// (acceleration and jerk).  PkT (S = double only): also the next sweep's
+// prologue into pk_next, ub_next and bpart_next (packets of PkOf<PkT>):
+// double / float, a Runge-Kutta stage's, from each star's next state and the
+// massive object's next position; Dual, the jerk sweep's at this state, with
+// the derivatives (v, a) of (x, v) from the acceleration just computed.
+// void: none.
 template <typename S, typename PkT = void>
 __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double* lds,
                                                double* fsum) {
@@ -831,10 +833,14 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   __syncthreads();
 
   constexpr bool CHAIN = !std::is_void<PkT>::value;
-  static_assert(!CHAIN || !DUAL, "chained stages are FP64 evaluations");
+  constexpr bool JNEXT = std::is_same<PkT, Dual>::value;  // the jerk sweep's packets
+  constexpr int NP = JNEXT ? 14 : 7;  // block-sum terms of the next prologue
+  static_assert(!CHAIN || !DUAL, "chained epilogues are FP64 evaluations");
   const int k = blk * kEpiStars + threadIdx.x;
   S bh[3] = {0.0, 0.0, 0.0};
-  double pro[7] = {0, 0, 0, 0, 0, 0, 0};
+  double pro[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) pro[q] = 0.0;
   if (threadIdx.x < kEpiStars && k < a.Ns) {
     const int i = k + 1;
     const int t = threadIdx.x;
@@ -929,10 +935,25 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
         for (int c = 0; c < 3; ++c) hermite_update(a, 3 * (size_t)i + c, at[c].v, at[c].d);
       }
     } else {
+      if constexpr (JNEXT) {
+        // the jerk sweep's prologue terms of this star (as k_prologue<Dual>
+        // computes them from pos_d = vel, vel_d = the acceleration)
+        const Dual x0d[3] = {Dual(x0, a.vel[0]), Dual(y0, a.vel[1]), Dual(z0, a.vel[2])};
+        const Dual xsd[3] = {Dual(xi, vi[0]), Dual(yi, vi[1]), Dual(zi, vi[2])};
+        const Dual vsd[3] = {Dual(vi[0], at[0]), Dual(vi[1], at[1]), Dual(vi[2], at[2])};
+        Dual pd[7];
+        star_terms<Dual, Dual>(x0d, xsd, vsd, a.mass[i], a.G, gM, a.eps2, a.pk_next, a.ub_next, k,
+                               pd);
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+          pro[q] = pd[q].v;
+          pro[7 + q] = pd[q].d;
+        }
+      }
       if (a.stage >= 0) {
         double xn[3] = {0.0, 0.0, 0.0}, vn[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < 3; ++c) rk4_update(a, 3 * (size_t)i + c, vi[c], at[c], xn[c], vn[c]);
-        if constexpr (CHAIN) {
+        if constexpr (CHAIN && !JNEXT) {
           // the massive object's next position, as k_bh_final will compute it
           double x0n[3];
           for (int c = 0; c < 3; ++c)
@@ -943,13 +964,13 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
       }
     }
   }
-  constexpr int NB = CHAIN ? 3 + 7 : 3 * W;
+  constexpr int NB = CHAIN ? 3 + NP : 3 * W;
   double bhs[NB];
 #pragma unroll
   for (int c = 0; c < 3; ++c) put(bhs, c, 3, bh[c]);
   if constexpr (CHAIN) {
 #pragma unroll
-    for (int q = 0; q < 7; ++q) bhs[3 + q] = pro[q];
+    for (int q = 0; q < NP; ++q) bhs[3 + q] = pro[q];
   }
   wave_sums<NB>(bhs, lds);  // the stars are in wavefront 0
   if (threadIdx.x < 4 * W) {
@@ -958,10 +979,12 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
     a.bhpart[(size_t)blk * 4 * W + threadIdx.x] = q < 3 ? lds[(h * 3 + q) * kBlock] : 0.0;
   }
   if constexpr (CHAIN) {
-    // the prologue's row layout: sum m b (3), sum m u, sum m v (3), 0
-    if (threadIdx.x >= 64 && threadIdx.x < 72) {
-      const int q = threadIdx.x - 64;
-      a.bpart_next[(size_t)blk * 8 + q] = q < 7 ? lds[(3 + q) * kBlock] : 0.0;
+    // the prologue's row layout: sum m b (3), sum m u, sum m v (3), 0 (and
+    // the same 8 columns of derivatives for the jerk sweep)
+    constexpr int RW = JNEXT ? 16 : 8;
+    if (threadIdx.x >= 64 && threadIdx.x < 64 + RW) {
+      const int c = threadIdx.x - 64, q = c & 7, h = c >> 3;
+      a.bpart_next[(size_t)blk * RW + c] = q < 7 ? lds[(3 + h * 7 + q) * kBlock] : 0.0;
     }
   }
 }
@@ -973,11 +996,11 @@ __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   epilogue_block<S>(a, blockIdx.x, lds, fsum);
 }
 
-// Runge-Kutta stage epilogue that also performs the next evaluation's
-// prologue (packets of PkOf<T>), saving that kernel's launch.
+// FP64 epilogue that also performs the next sweep's prologue (packets of
+// PkOf<T>; T = Dual: the jerk sweep at this state), saving that kernel.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_epilogue_chain(EpiArgs a) {
-  __shared__ double lds[10 * kBlock];
+  __shared__ double lds[(std::is_same<T, Dual>::value ? 17 : 10) * kBlock];
   __shared__ double fsum[kNF * kEpiStars];
   epilogue_block<double, T>(a, blockIdx.x, lds, fsum);
 }
@@ -1040,6 +1063,20 @@ template <typename S>
 __global__ __launch_bounds__(kBlock) void k_bh_final(EpiArgs a) {
   __shared__ double lds[(IsDual<S>::value ? 16 : 7) * kBlock];
   bh_final_block<S>(a, lds);
+}
+
+// The jerk evaluation's dual epilogue with the FP64 pass's massive-object
+// update (k_bh_final<double>'s work) in one extra workgroup: the dual
+// epilogue reads neither the massive object's FP64 acceleration nor the FP64
+// partial rows (its own rows are in separate buffers).
+__global__ __launch_bounds__(kBlock) void k_epilogue_dual_bh(EpiArgs a, EpiArgs e) {
+  __shared__ double lds[16 * kBlock];
+  __shared__ double fsum[kNF * 2 * kEpiStars];
+  if (blockIdx.x == gridDim.x - 1) {
+    bh_final_block<double>(e, lds);
+    return;
+  }
+  epilogue_block<Dual>(a, blockIdx.x, lds, fsum);
 }
 
 // The sweep of a chained Runge-Kutta stage with the previous stage's
