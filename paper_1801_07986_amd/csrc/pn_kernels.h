@@ -28,10 +28,20 @@
 // (only x, v, m and the O(N) massive-object terms u_j, b_j), so the potential
 // sweep and the 1PN sweep share one pass over j.
 //
+// Runge-Kutta steps chain their evaluations: k_epilogue_chain also performs
+// the next stage's prologue (each star's next state is in its registers), and
+// k_pair_bh is the sweep with one extra workgroup doing the previous stage's
+// k_bh_final work (the sweep reads only star packets), so a step is eight
+// kernels.  Massive-object block rows hold 64 stars in every kernel, summed
+// in the same tree, so whichever kernel writes a row it holds the same sum.
+//
 // The same four kernels instantiated on dual numbers (T = S = Dual) give the
 // time derivative of the force along the motion (the jerk of the Hermite
 // scheme), and their epilogue carries the Hermite corrector and predictor the
-// way the FP64 one carries the Runge-Kutta stage update.  Further down:
+// way the FP64 one carries the Runge-Kutta stage update.  In a jerk
+// evaluation the FP64 epilogue writes the dual packets (k_epilogue_chain<Dual>)
+// and the dual epilogue carries the FP64 massive-object update
+// (k_epilogue_dual_bh): six kernels.  Further down:
 // Eqs. (7)-(8) diagnostics (k_diag_*), close-encounter search (k_enc_*),
 // the unrestricted EIH equations (k_eih_*, reusing k_pair), and batched
 // ensembles (k_*_batched: one launch per phase for many systems).
