@@ -343,6 +343,30 @@ def test_full_size_n65536_mixed(pn):
     assert e.max() <= TOL_MIXED and e1.max() <= TOL_MIXED_1PN
 
 
+def test_full_size_n262144_mixed(pn):
+    """N = 262144 Plummer (M = 0.1, c = 30, eps = 1e-4), the largest single
+    system, mixed precision in its tuned launch shape: the 63 stars nearest to
+    the massive object and 448 random stars against the oracle row by row (a
+    star row costs the oracle O(N); the massive object's 1PN row would need
+    every star's sums, O(N^2)), and the massive object's Newtonian row through
+    Newtonian momentum conservation, sum_a m_a a^N_a = 0."""
+    w = inputs.WORKLOADS["plummer_n262144_mixed"]
+    pos, vel, mass = inputs.plummer_bh(w["N"], w["M_bh"], w["seed"])
+    print(f"[case] N={w['N']} mixed, shape {pn.pn_query_shape(1, w['N'])}", flush=True)
+    aN, phi, a1 = gpu_accel(pn, pos, vel, mass, w["c"], w["eps"], 1)
+    rows = _sample_rows(pos, 63, 448, 3)[1:]
+    rN, rphi, r1 = oracle.accel_rows(pos, vel, mass, G, w["c"], w["eps"], rows)
+    s = newton_scale(pos, mass, w["eps"], rows, chunk=32)
+    e = body_rel(aN[rows] + a1[rows], rN + r1, s)
+    e1 = body_rel(a1[rows], r1, s, 1e-6)
+    mom = np.abs((mass[:, None] * aN).sum(0)).max()
+    mom_scale = np.linalg.norm(mass[:, None] * aN, axis=1).sum()
+    print(f"N=262144 mixed: max rel total {e.max():.3e} median {np.median(e):.3e}, "
+          f"1PN max {e1.max():.3e}; |sum m a^N| / sum |m a^N| {mom / mom_scale:.2e}")
+    assert e.max() <= TOL_MIXED and e1.max() <= TOL_MIXED_1PN
+    assert mom <= 1e-6 * mom_scale
+
+
 def test_async_calls_on_two_streams_do_not_interfere(pn):
     """Two systems stepped with PN_ASYNC on two streams, back to back (they
     share the library's scratch): each ends exactly as when stepped alone."""
