@@ -74,6 +74,9 @@ def main() -> int:
                     help="--study: divide the workload's dt by this (same simulated time)")
     ap.add_argument("--hermite", type=int, default=0, metavar="STEPS",
                     help="only time STEPS fourth-order Hermite steps of the workload")
+    ap.add_argument("--ensemble", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS steps of the 256-system ensemble, batched and "
+                         "system by system")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB buffer 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -103,6 +106,10 @@ def main() -> int:
         return 0
     if args.table32:
         print(json.dumps(table32(pn, torch, inputs, args.samples, not args.no_cpu)), flush=True)
+        return 0
+    if args.ensemble:
+        print(json.dumps(ensemble(pn, torch, inputs, torch.cuda.current_stream(), args.ensemble)),
+              flush=True)
         return 0
     w = inputs.WORKLOADS[args.workload]
     N, c, eps, dt = w["N"], w["c"], w["eps"], w["dt"]
