@@ -158,3 +158,14 @@ def test_query_shape_follows_the_tuned_table(lib):
     assert lib.pn_query_shape(0, 1, ctypes.cast(out, ctypes.c_void_p)) == EINVAL
     assert lib.pn_query_shape(7, 100, ctypes.cast(out, ctypes.c_void_p)) == EINVAL
     assert lib.pn_query_shape(0, 100, None) == EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    (before touching torch or the GPU)."""
+    import sys
+
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr
