@@ -46,8 +46,8 @@ PEAK_FP32_VALU = 157.3e12
 TRAFFIC_BYTES = {
     # FETCH 6315.5 KiB, WRITE 46109.4 KiB per launch
     ("plummer_n16384_fp64", "k_pair_bh<double,3,2,4>", 32): 60150170,
-    # FETCH 79851.0 KiB, WRITE 188669.4 KiB per launch
-    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 32): 356732314,
+    # FETCH 64259.4 KiB, WRITE 141502.1 KiB per launch
+    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 24): 276501402,
 }
 
 

@@ -1,13 +1,18 @@
 """Launch-shape autotuner for the star-star sweep.
 
-For each precision and a ladder of system sizes it times complete force
-evaluations (prologue, pair sweep, epilogue; pn_accel on the caller's stream,
-HIP events around it) over the candidate shapes
+For each precision and a ladder of system sizes it times whole RK4 steps
+(pn_step: the chained sequence of sweeps and epilogues, replayed as a graph;
+wall clock around a run of steps on the caller's stream) over the candidate
+shapes
 
     ipt in {1, 2}   i-bodies per lane
     ws in {1, 4}    wavefronts sharing one i-range
-    nsplit          j-range splits (powers of two with at least 32 j per
-                    wavefront, or 0 = the library's default rule)
+    nsplit          j-range splits (at least 4 j per wavefront, or 0 = the
+                    library's default rule)
+
+At small N the step is latency-bound and more splits (shorter j-loops on
+more SIMDs) pay even at a few j per wavefront; at large N the sweep is
+compute-bound and the split count matters little.
 
 and writes the fastest shape per size as a table of N-ranges (boundaries at
 the geometric midpoints between measured sizes) to ``tuned_shapes.json``,
@@ -26,35 +31,40 @@ import os
 import sys
 import time
 
-SIZES = [1024, 2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144]
-QUICK_SIZES = [1024, 4096, 16384, 65536]
+SIZES = [100, 300, 1024, 2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144]
+QUICK_SIZES = [100, 1024, 4096, 16384, 65536]
+SPLITS = (0, 1, 2, 4, 8, 12, 16, 24, 32, 48, 64, 128)
 
 
 def candidates(N: int):
     """(ipt, ws, nsplit); nsplit 0 is the library's default rule for that N."""
     Ns = N - 1
     for ipt, ws in itertools.product((1, 2), (1, 4)):
-        for ns in (0, 1, 2, 4, 8, 16, 32, 64, 128):
-            if ns <= 1 or ns <= max(1, Ns // (32 * ws)):
+        for ns in SPLITS:
+            if ns <= 1 or ns <= max(1, Ns // (4 * ws)):
                 yield ipt, ws, ns
 
 
-def time_eval(pn, torch, P, V, Mm, out, prec, reps_min=3, budget_s=0.05):
+def time_step(pn, torch, P, V, Mm, prec, budget_s=0.05, reps=3):
+    """Best of `reps` runs of whole RK4 steps (each run at least budget_s of
+    wall clock); ms per step.  The first call captures the step graph."""
     stream = torch.cuda.current_stream()
-    pn.pn_accel(P, V, Mm, 1.0, 30.0, 1e-4, prec, out, None, None, stream=stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps, total = 0, 0.0
-    while reps < reps_min or total < budget_s * 1e3:
-        e0.record(stream)
-        pn.pn_accel(P, V, Mm, 1.0, 30.0, 1e-4, prec, out, None, None, stream=stream,
-                    flags=pn.PN_ASYNC)
-        e1.record(stream)
-        e1.synchronize()
-        total += e0.elapsed_time(e1)
-        reps += 1
-        if reps >= 50:
-            break
-    return total / reps
+    pn.pn_step(P, V, Mm, 1.0, 30.0, 1e-4, 1e-7, 2, prec, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pn.pn_step(P, V, Mm, 1.0, 30.0, 1e-4, 1e-7, 1, prec, stream=stream)
+    torch.cuda.synchronize()
+    one = max(time.perf_counter() - t0, 1e-6)
+    steps = max(1, min(2000, int(budget_s / one)))
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pn.pn_step(P, V, Mm, 1.0, 30.0, 1e-4, 1e-7, steps, prec, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        best = ms if best is None else min(best, ms)
+    return best
 
 
 def tune(sizes, log=print):
@@ -71,21 +81,21 @@ def tune(sizes, log=print):
         P = torch.from_numpy(pos).cuda()
         V = torch.from_numpy(vel).cuda()
         Mm = torch.from_numpy(mass).cuda()
-        out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
         for prec_name, prec in (("fp64", pn.PN_FP64), ("mixed", pn.PN_MIXED)):
             best = None
             for ipt, ws, ns in candidates(N):
                 os.environ["PN_SHAPE"] = f"{ipt},{ws},{ns}"
-                ms = time_eval(pn, torch, P, V, Mm, out, prec)
+                ms = time_step(pn, torch, P, V, Mm, prec)
+                log(f"[autotune]   N={N} {prec_name} ipt={ipt} ws={ws} nsplit={ns}: {ms:.4f} ms/step")
                 if best is None or ms < best[0]:
                     best = (ms, ipt, ws, ns)
             os.environ.pop("PN_SHAPE", None)
-            default_ms = time_eval(pn, torch, P, V, Mm, out, prec)
+            default_ms = time_step(pn, torch, P, V, Mm, prec)
             ms, ipt, ws, ns = best
             results.append(dict(N=N, precision=prec_name, ipt=ipt, ws=ws, nsplit=ns,
-                                eval_ms=ms, default_eval_ms=default_ms))
+                                step_ms=ms, default_step_ms=default_ms))
             log(f"[autotune] N={N} {prec_name}: best ipt={ipt} ws={ws} nsplit={ns} "
-                f"{ms:.4f} ms/eval (default rule {default_ms:.4f} ms)")
+                f"{ms:.4f} ms/step (default rule {default_ms:.4f} ms)")
     return results
 
 
@@ -98,8 +108,8 @@ def to_table(results):
             hi = (1 << 28) if k == len(rows) - 1 else int(math.sqrt(r["N"] * rows[k + 1]["N"]))
             entries.append(dict(precision=prec, n_min=lo, n_max=hi, ipt=r["ipt"], ws=r["ws"],
                                 nsplit=r["nsplit"], measured_N=r["N"],
-                                eval_ms=round(r["eval_ms"], 5),
-                                default_eval_ms=round(r["default_eval_ms"], 5)))
+                                step_ms=round(r["step_ms"], 5),
+                                default_step_ms=round(r["default_step_ms"], 5)))
     return {"device": "MI355X (gfx950)", "tool": "paper_1801_07986_amd.autotune",
             "created": time.strftime("%Y-%m-%d %H:%M:%S"), "entries": entries}
 

@@ -80,8 +80,9 @@ Shape pick_shape(int Ns, int precision) {
   const int ib = kBlock / s.ws * s.ipt;  // i-bodies per workgroup
   s.iblocks = (Ns + ib - 1) / ib;
   if (want_nsplit <= 0) {
+    // default: about 4096 sweep workgroups, but at least 16 j per wavefront
     want_nsplit = std::max(16, (4096 + s.iblocks - 1) / s.iblocks);
-    want_nsplit = std::min(want_nsplit, std::max(1, Ns / (32 * s.ws)));
+    want_nsplit = std::min(want_nsplit, std::max(1, Ns / (16 * s.ws)));
   }
   want_nsplit = std::max(1, std::min(want_nsplit, Ns));
   s.jchunk = (Ns + want_nsplit - 1) / want_nsplit;
