@@ -67,6 +67,10 @@ def _load():
                            ctypes.c_double, ctypes.c_double, _dp, _dp],
             "pnref_hermite": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, _i64, ctypes.c_double],
+            "pnref_jerk_rows": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, _i64p, _i64, _dp, _dp],
+            "pnref_jerk_exact": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, _dp, _dp],
         }
         for name, argtypes in sig.items():
             fn = getattr(lib, name)
@@ -192,8 +196,29 @@ def jerk(pos, vel, mass, G, c, eps, h=1e-4):
     return a, j
 
 
-def hermite(pos, vel, mass, G, c, eps, dt, nsteps, h=1e-4):
-    """Advance copies of (pos, vel) by nsteps fixed Hermite steps; returns them."""
+def jerk_exact(pos, vel, mass, G, c, eps, rows=None):
+    """(acceleration, jerk along the motion) by complex-step differentiation:
+    exact to rounding.  ``rows``: body indices (default all); star rows cost
+    O(N) each after one O(N^2) evaluation, the massive object's row O(N^2)."""
+    N = len(mass)
+    pos, vel, mass = _arr(pos, (N, 3)), _arr(vel, (N, 3)), _arr(mass, (N,))
+    if rows is None:
+        a, j = np.empty((N, 3)), np.empty((N, 3))
+        _check(_load().pnref_jerk_exact(_p(pos), _p(vel), _p(mass), N, G, c, eps, _p(a), _p(j)),
+               "pnref_jerk_exact")
+        return a, j
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    R = len(rows)
+    a, j = np.empty((R, 3)), np.empty((R, 3))
+    _check(_load().pnref_jerk_rows(_p(pos), _p(vel), _p(mass), N, G, c, eps,
+                                   rows.ctypes.data_as(_i64p), R, _p(a), _p(j)),
+           "pnref_jerk_rows")
+    return a, j
+
+
+def hermite(pos, vel, mass, G, c, eps, dt, nsteps, h=0.0):
+    """Advance copies of (pos, vel) by nsteps fixed Hermite steps; returns them.
+    Jerks are exact (complex step) for h = 0, else Richardson quotients of step h."""
     N = len(mass)
     pos, vel, mass = _arr(pos, (N, 3)).copy(), _arr(vel, (N, 3)).copy(), _arr(mass, (N,))
     _check(_load().pnref_hermite(_p(pos), _p(vel), _p(mass), N, G, c, eps, dt, nsteps, h),

@@ -29,6 +29,7 @@
  * operation in source order.  OpenMP (when enabled) only distributes the outer
  * per-body loop; each body's sums run sequentially in index order.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -764,6 +765,182 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
+/* Exact jerk by complex-step differentiation (Lyness & Moler 1967;     */
+/* Squire & Trapp 1998).  For f analytic along the path,               */
+/*   f(x + i h d) = f(x) + i h f'(x) d + O(h^2),                        */
+/* so Re f = f(x) and Im f / h = f'(x) d to rounding: there is no       */
+/* difference of nearby values, hence no cancellation, and with h tiny  */
+/* (1e-20 here) the O(h^2) remainder is far below one ulp.  The limited-*/
+/* 1PN acceleration (the definition of pnref_accel, written out again   */
+/* below in complex arithmetic) is evaluated at positions x + i h v and */
+/* velocities v + i h a, with a = pnref_accel's acceleration: this is    */
+/* the derivative along the motion, jerk = (v.grad_x + a.grad_v) a.     */
+/* Every operation is analytic -- sums, products, quotients and the     */
+/* principal square root of numbers with positive real part -- and no  */
+/* branch depends on a complex value.                                    */
+/* ------------------------------------------------------------------ */
+typedef double complex cpx;
+
+static const double kCsH = 1e-20; /* complex step */
+
+static cpx cdot3(const cpx *a, const cpx *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* d = xa - xb; returns R = sqrt(|d|^2 + eps^2) (principal root) */
+static cpx csep(const cpx *xa, const cpx *xb, double eps2, cpx *d) {
+  for (int q = 0; q < 3; ++q) d[q] = xa[q] - xb[q];
+  return csqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2);
+}
+
+/* rows: nrows indices into 0..N-1; acc_out, jerk_out: [nrows][3] in that
+   order.  Star rows cost O(N) each on top of one real evaluation of all
+   bodies (the direction a); the massive object's row needs every star's
+   potential and Newtonian acceleration, one more O(N^2) pass. */
+int pnref_jerk_rows(const double *pos, const double *vel, const double *mass, idx_t N, double G,
+                    double c, double eps, const idx_t *rows, idx_t nrows, double *acc_out,
+                    double *jerk_out) {
+  int rc = check_common(pos, mass, N, G, eps);
+  if (rc) return rc;
+  if (check_c(c) || !vel || !rows || nrows < 0 || !acc_out || !jerk_out) return PNREF_EINVAL;
+  for (idx_t r = 0; r < nrows; ++r)
+    if (rows[r] < 0 || rows[r] >= N) return PNREF_EINVAL;
+  const idx_t n3 = 3 * N;
+  const double lam = lambda_of(c), eps2 = eps * eps, M = mass[0], h = kCsH;
+  double *ra = (double *)malloc(sizeof(double) * (size_t)(2 * n3 + N));
+  cpx *X = (cpx *)malloc(sizeof(cpx) * (size_t)n3);
+  cpx *W = (cpx *)malloc(sizeof(cpx) * (size_t)n3);
+  cpx *u = (cpx *)malloc(sizeof(cpx) * (size_t)N);
+  cpx *b = (cpx *)malloc(sizeof(cpx) * (size_t)n3);
+  cpx *V = (cpx *)malloc(sizeof(cpx) * (size_t)N);
+  cpx *aN = (cpx *)malloc(sizeof(cpx) * (size_t)n3);
+  char *want = (char *)calloc((size_t)N, 1);
+  if (!ra || !X || !W || !u || !b || !V || !aN || !want) {
+    rc = PNREF_ENOMEM;
+    goto done;
+  }
+  /* the direction of the velocities: the acceleration itself */
+  {
+    double *raN = ra, *ra1 = ra + n3, *rph = ra + 2 * n3;
+    if ((rc = pnref_accel(pos, vel, mass, N, G, c, eps, raN, rph, ra1))) goto done;
+    for (idx_t t = 0; t < n3; ++t) {
+      X[t] = pos[t] + I * (h * vel[t]);
+      W[t] = vel[t] + I * (h * (raN[t] + ra1[t]));
+    }
+  }
+  /* massive object's potential u_s = G M / R_s0 and pull b_s at each star */
+  u[0] = 0.0;
+  b[0] = b[1] = b[2] = 0.0;
+  for (idx_t s = 1; s < N; ++s) {
+    cpx d[3];
+    cpx R = csep(X + 3 * s, X, eps2, d);
+    u[s] = G * M / R;
+    for (int q = 0; q < 3; ++q) b[3 * s + q] = G * M * d[q] / (R * R * R);
+  }
+  /* w = -P/M, P = sum_s m_s v_s */
+  cpx w[3] = {0.0, 0.0, 0.0};
+  for (idx_t s = 1; s < N; ++s)
+    for (int q = 0; q < 3; ++q) w[q] += mass[s] * W[3 * s + q];
+  for (int q = 0; q < 3; ++q) w[q] = -w[q] / M;
+  /* Newtonian potential magnitude V_a and acceleration aN_a: the massive
+     object, the requested rows, and every body if the massive object's
+     row is requested */
+  want[0] = 1;
+  for (idx_t r = 0; r < nrows; ++r) {
+    want[rows[r]] = 1;
+    if (rows[r] == 0) memset(want, 1, (size_t)N);
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (idx_t a = 0; a < N; ++a) {
+    if (!want[a]) continue;
+    cpx Va = 0.0, g[3] = {0.0, 0.0, 0.0}, d[3];
+    for (idx_t e = 0; e < N; ++e) {
+      if (e == a) continue;
+      cpx R = csep(X + 3 * a, X + 3 * e, eps2, d);
+      Va += G * mass[e] / R;
+      for (int q = 0; q < 3; ++q) g[q] -= G * mass[e] * d[q] / (R * R * R);
+    }
+    V[a] = Va;
+    for (int q = 0; q < 3; ++q) aN[3 * a + q] = g[q];
+  }
+  const cpx *x0 = X, *aN0 = aN;
+  const cpx V0 = V[0];
+#pragma omp parallel for schedule(dynamic, 1)
+  for (idx_t r = 0; r < nrows; ++r) {
+    const idx_t i = rows[r];
+    cpx pn[3] = {0.0, 0.0, 0.0};
+    if (i == 0) {
+      /* massive object: one term per star s */
+      for (idx_t s = 1; s < N; ++s) {
+        const cpx *vs = W + 3 * s, *as = aN + 3 * s;
+        cpx d[3];
+        cpx R = csep(x0, X + 3 * s, eps2, d);
+        cpx n[3] = {d[0] / R, d[1] / R, d[2] / R};
+        cpx k = G * mass[s] / (R * R), nv = cdot3(n, vs), nw = cdot3(n, w);
+        cpx br = -2.0 * cdot3(vs, vs) + 4.0 * cdot3(w, vs) + 1.5 * nv * nv + 4.0 * V0 + V[s] +
+                 0.5 * cdot3(d, as);
+        for (int q = 0; q < 3; ++q)
+          pn[q] += k * (br * n[q] + 3.0 * nv * vs[q] - 3.0 * nv * w[q] - 4.0 * nw * vs[q]) +
+                   3.5 * (G * mass[s] / R) * as[q];
+      }
+    } else {
+      const cpx *xi = X + 3 * i, *vi = W + 3 * i;
+      const cpx vi2 = cdot3(vi, vi);
+      /* partner: the massive object */
+      {
+        cpx d[3];
+        cpx R = csep(xi, x0, eps2, d);
+        cpx n[3] = {d[0] / R, d[1] / R, d[2] / R};
+        cpx k = G * M / (R * R), nw = cdot3(n, w), n4v = 4.0 * cdot3(n, vi);
+        cpx br = -vi2 + 4.0 * cdot3(vi, w) + 4.0 * V[i] + V0 + 0.5 * cdot3(d, aN0);
+        for (int q = 0; q < 3; ++q)
+          pn[q] += k * (br * n[q] + n4v * (vi[q] - w[q]) - 3.0 * nw * vi[q]) +
+                   3.5 * (G * M / R) * aN0[q];
+      }
+      /* partners: stars j != i */
+      for (idx_t j = 1; j < N; ++j) {
+        if (j == i) continue;
+        const cpx *vj = W + 3 * j, *bj = b + 3 * j;
+        cpx d[3];
+        cpx R = csep(xi, X + 3 * j, eps2, d);
+        cpx n[3] = {d[0] / R, d[1] / R, d[2] / R};
+        cpx k = G * mass[j] / (R * R), nv = cdot3(n, vj);
+        cpx S = -vi2 - 2.0 * cdot3(vj, vj) + 4.0 * cdot3(vi, vj) + 1.5 * nv * nv + 4.0 * u[i] +
+                u[j] - 0.5 * cdot3(d, bj);
+        cpx D = 4.0 * cdot3(n, vi) - 3.0 * nv;
+        for (int q = 0; q < 3; ++q)
+          pn[q] += k * (S * n[q] + D * (vi[q] - vj[q])) - 3.5 * (G * mass[j] / R) * bj[q];
+      }
+    }
+    for (int q = 0; q < 3; ++q) {
+      cpx tot = aN[3 * i + q] + lam * pn[q];
+      acc_out[3 * r + q] = creal(tot);
+      jerk_out[3 * r + q] = cimag(tot) / h;
+    }
+  }
+done:
+  free(ra);
+  free(X);
+  free(W);
+  free(u);
+  free(b);
+  free(V);
+  free(aN);
+  free(want);
+  return rc;
+}
+
+/* All N bodies (rows 0..N-1). */
+int pnref_jerk_exact(const double *pos, const double *vel, const double *mass, idx_t N, double G,
+                     double c, double eps, double *acc_out, double *jerk_out) {
+  if (N < 2) return PNREF_EINVAL;
+  idx_t *rows = (idx_t *)malloc(sizeof(idx_t) * (size_t)N);
+  if (!rows) return PNREF_ENOMEM;
+  for (idx_t r = 0; r < N; ++r) rows[r] = r;
+  int rc = pnref_jerk_rows(pos, vel, mass, N, G, c, eps, rows, N, acc_out, jerk_out);
+  free(rows);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Fourth-order Hermite scheme with a fixed step (predict, evaluate,    */
 /* correct), the scheme the paper names as the remedy for close          */
 /* encounters (Sec. 4-5):                                               */
@@ -778,13 +955,21 @@ done:
 /* and are zero before the first step.  The velocity-dependent 1PN force */
 /* makes the predicted velocity matter: with the plain predictor         */
 /* (a and j only) its O(dt^3) error would leave the scheme third order.  */
-/* Jerks from pnref_jerk with difference step h.                         */
+/* Jerks from pnref_jerk with difference step h, or, with h = 0, the    */
+/* exact ones of pnref_jerk_exact.                                       */
 /* ------------------------------------------------------------------ */
+static int jerk_of(const double *pos, const double *vel, const double *mass, idx_t N, double G,
+                   double c, double eps, double h, double *acc, double *jerk) {
+  if (h == 0.0) return pnref_jerk_exact(pos, vel, mass, N, G, c, eps, acc, jerk);
+  return pnref_jerk(pos, vel, mass, N, G, c, eps, h, acc, jerk);
+}
+
 int pnref_hermite(double *pos, double *vel, const double *mass, idx_t N, double G, double c,
                   double eps, double dt, idx_t nsteps, double h) {
   int rc = check_common(pos, mass, N, G, eps);
   if (rc) return rc;
-  if (check_c(c) || !vel || !isfinite(dt) || !(dt > 0.0) || nsteps < 0 || !(h > 0.0))
+  if (check_c(c) || !vel || !isfinite(dt) || !(dt > 0.0) || nsteps < 0 || !(h >= 0.0) ||
+      !isfinite(h))
     return PNREF_EINVAL;
   const idx_t n3 = 3 * N;
   double *buf = (double *)malloc(sizeof(double) * (size_t)n3 * 8);
@@ -792,7 +977,7 @@ int pnref_hermite(double *pos, double *vel, const double *mass, idx_t N, double 
   double *a = buf, *j = a + n3, *sn = j + n3, *cr = sn + n3, *xp = cr + n3, *vp = xp + n3,
          *ap = vp + n3, *jp = ap + n3;
   const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
-  if ((rc = pnref_jerk(pos, vel, mass, N, G, c, eps, h, a, j))) goto done;
+  if ((rc = jerk_of(pos, vel, mass, N, G, c, eps, h, a, j))) goto done;
   for (idx_t t = 0; t < n3; ++t) sn[t] = cr[t] = 0.0;
   for (idx_t step = 0; step < nsteps; ++step) {
     for (idx_t t = 0; t < n3; ++t) {
@@ -800,7 +985,7 @@ int pnref_hermite(double *pos, double *vel, const double *mass, idx_t N, double 
               dt5 / 120.0 * cr[t];
       vp[t] = vel[t] + dt * a[t] + dt2 / 2.0 * j[t] + dt3 / 6.0 * sn[t] + dt4 / 24.0 * cr[t];
     }
-    if ((rc = pnref_jerk(xp, vp, mass, N, G, c, eps, h, ap, jp))) break;
+    if ((rc = jerk_of(xp, vp, mass, N, G, c, eps, h, ap, jp))) break;
     for (idx_t t = 0; t < n3; ++t) {
       double vn = vel[t] + dt / 2.0 * (a[t] + ap[t]) + dt2 / 12.0 * (j[t] - jp[t]);
       pos[t] = pos[t] + dt / 2.0 * (vel[t] + vn) + dt2 / 12.0 * (a[t] - ap[t]);

@@ -61,6 +61,17 @@ MUTATIONS = [
      "vp[t] = vel[t] + dt * a[t] + dt2 / 2.0 * j[t];"),
     ("hermite_crackle_sign", "+ 6.0 * dt * (j[t] + jp[t])) / dt3;",
      "- 6.0 * dt * (j[t] + jp[t])) / dt3;"),
+    ("jerk_exact_velocity_direction_newtonian_only",
+     "W[t] = vel[t] + I * (h * (raN[t] + ra1[t]));", "W[t] = vel[t] + I * (h * raN[t]);"),
+    ("jerk_exact_no_position_direction", "X[t] = pos[t] + I * (h * vel[t]);", "X[t] = pos[t];"),
+    ("jerk_exact_w_from_unperturbed_velocities",
+     "for (int q = 0; q < 3; ++q) w[q] += mass[s] * W[3 * s + q];",
+     "for (int q = 0; q < 3; ++q) w[q] += mass[s] * vel[3 * s + q];"),
+    ("jerk_exact_star_half_xb_sign", "u[j] - 0.5 * cdot3(d, bj);", "u[j] + 0.5 * cdot3(d, bj);"),
+    ("jerk_exact_bh_Vs_sign", "4.0 * V0 + V[s] +", "4.0 * V0 - V[s] +"),
+    ("jerk_exact_b_of_unperturbed_position",
+     "for (int q = 0; q < 3; ++q) b[3 * s + q] = G * M * d[q] / (R * R * R);",
+     "for (int q = 0; q < 3; ++q) b[3 * s + q] = G * M * creal(d[q]) / (R * R * R);"),
 ]
 
 # the pins run against each mutant (the mutation test must not rely on P6's
@@ -78,8 +89,14 @@ PIN_CALLS = [
     lambda m: pins.test_p10_plummer_softening_closed_form(m),
     lambda m: pins.test_jerk_newtonian_closed_form(m),
     lambda m: pins.test_jerk_is_the_time_derivative_along_the_motion(m),
-    lambda m: pins.test_hermite_fourth_order_and_precession(m),
-    lambda m: pins.test_hermite_fourth_order_with_velocity_dependent_force(m),
+    lambda m: pins.test_hermite_fourth_order_and_precession(m, 2e-5),
+    lambda m: pins.test_hermite_fourth_order_with_velocity_dependent_force(m, 3e-5),
+    lambda m: pins.test_jerk_exact_value_part_is_the_acceleration(m, 3.0),
+    lambda m: pins.test_jerk_exact_newtonian_closed_form(m, 1e-2),
+    lambda m: pins.test_jerk_exact_two_body_closed_form(m),
+    lambda m: pins.test_difference_quotient_converges_to_exact_jerk_as_h4(m, 3.0),
+    lambda m: pins.test_jerk_exact_is_the_time_derivative_along_the_motion(m),
+    lambda m: pins.test_hermite_fourth_order_with_velocity_dependent_force(m, 0.0),
 ]
 
 

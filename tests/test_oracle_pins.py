@@ -443,22 +443,121 @@ def test_jerk_is_the_time_derivative_along_the_motion(oracle_mod):
     assert np.abs(jt - j).max() <= 1e-9 * np.abs(j).max()
 
 
-def test_hermite_fourth_order_with_velocity_dependent_force(oracle_mod):
+# ------------------------------------------------ exact jerk (complex step)
+def _moving_cluster(seed=7, N=40):
+    """A random cluster with a moving massive object (w != 0 and v_0 != 0)."""
+    pos, vel, mass = random_cluster(N, seed, M=0.3)
+    vel = vel.copy()
+    vel[0] = [0.05, -0.02, 0.03]
+    return pos, vel, mass
+
+
+def _newton_jerk(pos, vel, mass, eps):
+    """Softened Newtonian jerk, textbook closed form:
+    j_a = -sum_b G m_b [v_ab / R^3 - 3 (x_ab . v_ab) x_ab / R^5]."""
+    d = pos[:, None, :] - pos[None, :, :]
+    dv = vel[:, None, :] - vel[None, :, :]
+    R2 = (d * d).sum(-1) + eps * eps
+    np.fill_diagonal(R2, np.inf)
+    R3 = R2 ** 1.5
+    t = dv / R3[..., None] - 3.0 * ((d * dv).sum(-1) / (R3 * R2))[..., None] * d
+    return -(G * mass[None, :, None] * t).sum(1)
+
+
+@pytest.mark.parametrize("c", [3.0, 30.0])
+def test_jerk_exact_value_part_is_the_acceleration(oracle_mod, c):
+    """The complex-step evaluation is a second, independent transcription of
+    the limited-1PN acceleration: its real part equals pnref_accel's."""
+    pos, vel, mass = _moving_cluster()
+    a, _ = oracle_mod.jerk_exact(pos, vel, mass, G, c, 1e-3)
+    aN, _, a1 = oracle_mod.accel(pos, vel, mass, G, c, 1e-3)
+    ref = aN + a1
+    err = (np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
+    assert err <= 1e-15
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-2])
+def test_jerk_exact_newtonian_closed_form(oracle_mod, eps):
+    """c = inf: the jerk equals the softened Newtonian closed form to rounding."""
+    pos, vel, mass = _moving_cluster(8)
+    _, j = oracle_mod.jerk_exact(pos, vel, mass, G, np.inf, eps)
+    ref = _newton_jerk(pos, vel, mass, eps)
+    err = (np.linalg.norm(j - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
+    assert err <= 1e-13
+
+
+def test_jerk_exact_two_body_closed_form(oracle_mod):
+    M, m = 1.0, 1e-3
+    x, v = np.array([0.7, -0.2, 0.3]), np.array([0.1, 0.9, -0.2])
+    pos, vel, mass = np.array([[0, 0, 0], x]), np.array([[0, 0, 0], v]), np.array([M, m])
+    _, j = oracle_mod.jerk_exact(pos, vel, mass, G, np.inf, 0.0)
+    r = np.linalg.norm(x)
+    jex = -G * M * (v / r**3 - 3 * (x @ v) * x / r**5)
+    assert np.abs(j[1] - jex).max() <= 1e-15 * np.abs(jex).max()
+
+
+@pytest.mark.parametrize("c", [3.0, 30.0])
+def test_difference_quotient_converges_to_exact_jerk_as_h4(oracle_mod, c):
+    """The Richardson quotient of the acceleration along the motion approaches
+    the complex-step jerk at the quotient's own rate, h^4 (ratio 16 per
+    halving), down to ~5e-9: so the complex-step jerk is the derivative of
+    the very acceleration, 1PN terms included (c = 3: 1PN is a large share)."""
+    pos, vel, mass = _moving_cluster(9)
+    eps = 1e-2
+    _, j = oracle_mod.jerk_exact(pos, vel, mass, G, c, eps)
+    errs = [np.abs(oracle_mod.jerk(pos, vel, mass, G, c, eps, h=h)[1] - j).max() / np.abs(j).max()
+            for h in (4e-3, 2e-3, 1e-3)]
+    assert 15.5 < errs[0] / errs[1] < 16.5 and 15.5 < errs[1] / errs[2] < 16.5
+    assert errs[2] < 1e-8
+
+
+def test_jerk_exact_is_the_time_derivative_along_the_motion(oracle_mod):
+    """The exact jerk equals a five-point time derivative of the oracle's
+    accelerations at states its RK4 integrator reaches at t = +-tau, +-2 tau
+    (c = 3); the five-point rule's own error is ~1e-10 here."""
+    pos, vel, mass = _circ_cluster(5, ns=4, mstar=1e-2)
+    c, eps, tau = 3.0, 1e-3, 1e-3
+    _, j = oracle_mod.jerk_exact(pos, vel, mass, G, c, eps)
+
+    def acc_at(t, sub=20):
+        p, v = oracle_mod.step(pos, vel, mass, G, c, eps, t / sub, sub)
+        aN, _, a1 = oracle_mod.accel(p, v, mass, G, c, eps)
+        return aN + a1
+
+    jt = (8 * (acc_at(tau) - acc_at(-tau)) - (acc_at(2 * tau) - acc_at(-2 * tau))) / (12 * tau)
+    assert np.abs(jt - j).max() <= 1e-9 * np.abs(j).max()
+
+
+def test_jerk_exact_rows_equal_all_bodies(oracle_mod):
+    pos, vel, mass = _moving_cluster(10)
+    a, j = oracle_mod.jerk_exact(pos, vel, mass, G, 5.0, 1e-3)
+    rows = np.array([7, 0, 39, 1, 7])
+    ar, jr = oracle_mod.jerk_exact(pos, vel, mass, G, 5.0, 1e-3, rows)
+    assert np.array_equal(ar, a[rows]) and np.array_equal(jr, j[rows])
+    # star rows alone (no massive-object row) take the O(N) path
+    ar, jr = oracle_mod.jerk_exact(pos, vel, mass, G, 5.0, 1e-3, rows[rows > 0])
+    assert np.array_equal(ar, a[rows[rows > 0]]) and np.array_equal(jr, j[rows[rows > 0]])
+
+
+@pytest.mark.parametrize("h", [3e-5, 0.0])
+def test_hermite_fourth_order_with_velocity_dependent_force(oracle_mod, h):
     """With a strongly velocity-dependent force (c = 3) the scheme stays fourth
     order (ratio ~16 per halving of dt at t = 1; a velocity predicted without
-    snap and crackle gives ~8 here)."""
+    snap and crackle gives ~8 here), with difference-quotient jerks (h > 0)
+    and with exact ones (h = 0)."""
     pos, vel, mass = _circ_cluster(5, ns=4, mstar=1e-2)
     c, eps, T = 3.0, 1e-3, 1.0
 
     def run(n):
-        return oracle_mod.hermite(pos, vel, mass, G, c, eps, T / n, n, h=3e-5)[0]
+        return oracle_mod.hermite(pos, vel, mass, G, c, eps, T / n, n, h=h)[0]
 
     ref = run(1600)
     e = [np.abs(run(n) - ref).max() for n in (50, 100, 200)]
     assert 13 < e[0] / e[1] < 19 and 13 < e[1] / e[2] < 19
 
 
-def test_hermite_fourth_order_and_precession(oracle_mod):
+@pytest.mark.parametrize("h", [2e-5, 0.0])
+def test_hermite_fourth_order_and_precession(oracle_mod, h):
     """The Hermite scheme integrates the same equations as RK4 to fourth
     order: halving dt cuts the one-orbit error ~16x, and the results of both
     integrators agree."""
@@ -472,7 +571,7 @@ def test_hermite_fourth_order_and_precession(oracle_mod):
     ref, _ = oracle_mod.step(pos, vel, mass, G, c, 0.0, T / 8000, 8000)
     errs = []
     for n in (500, 1000):
-        p, _ = oracle_mod.hermite(pos, vel, mass, G, c, 0.0, T / n, n, h=2e-5)
+        p, _ = oracle_mod.hermite(pos, vel, mass, G, c, 0.0, T / n, n, h=h)
         errs.append(np.abs(p[1] - ref[1]).max())
     assert 12 < errs[0] / errs[1] < 20
     assert errs[1] < 1e-6
