@@ -110,6 +110,34 @@ int pn_accel(const double* pos, const double* vel, const double* mass, int64_t N
              double* acc_1pn, void* stream, int flags);
 
 /*
+ * pn_accel for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, outputs and error codes as pn_accel, and the same kernels; the
+ * call makes no device allocation and no hipFree.  Its scratch (star packets,
+ * the sweep's per-split partial sums, block rows, the status word) is a fixed
+ * 64 MiB device array that the library's code object holds on every GPU it
+ * is loaded on, until the process ends.
+ * - Limit: the partial sums take 88 bytes per star and j-split; where
+ *   pn_accel's split count would not fit, fewer splits are used (results then
+ *   differ from pn_accel's by rounding only), and N whose scratch exceeds
+ *   64 MiB even with one split (about N > 300000) is rejected with PN_EINVAL
+ *   before any device work (pn_strerror(PN_EINVAL) names the sizes).
+ * - Calls on one GPU share that array and it keeps the last call's contents
+ *   (each call rewrites everything it reads, its status word included): calls
+ *   that overlap on one GPU, from different streams or host threads racing
+ *   with PN_ASYNC, race.  Calls of the other entry points use their own
+ *   scratch and do not race with it.
+ * - The first call of the library on a device (any entry point) sets the
+ *   device up: it creates the library's stream and looks up the array's
+ *   device address.  Make one such call before capturing.  Under capture pass
+ *   the capturing stream and PN_ASYNC (a synchronous call waits for the
+ *   stream).  PN_TIMING is rejected (it would create events).
+ */
+int pn_accel_noalloc(const double* pos, const double* vel, const double* mass, int64_t N,
+                     double G, double c, double eps, int precision, double* acc_newton,
+                     double* phi, double* acc_1pn, void* stream, int flags);
+
+/*
  * Unrestricted EIH 1PN accelerations of all N bodies: every pair at full 1PN
  * order, with no body singled out (the general N-body 1PN equations the paper
  * starts from in Sec. 2 and names as its next step in Sec. 5).  Evaluated in

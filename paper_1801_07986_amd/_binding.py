@@ -20,7 +20,7 @@ PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
 
 EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
            "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape",
-           "pn_accel_eih", "pn_encounters", "pn_jerk", "pn_step_hermite", "pn_query_shape")
+           "pn_accel_eih", "pn_encounters", "pn_jerk", "pn_step_hermite", "pn_query_shape", "pn_accel_noalloc")
 TUNED_PATH = os.path.join(HERE, "tuned_shapes.json")
 
 
@@ -45,6 +45,7 @@ def load():
         lib.pn_potential_accel.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, i32]
         lib.pn_correction.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, vp, vp, i32]
         lib.pn_accel.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
+        lib.pn_accel_noalloc.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
         lib.pn_accel_eih.argtypes = [vp, vp, vp, i64, d, d, d, i32, vp, vp, vp, vp, i32]
         lib.pn_encounters.argtypes = [vp, vp, vp, i64, d, d, d, vp, vp, i32]
         lib.pn_step.argtypes = [vp, vp, vp, i64, d, d, d, d, i64, i32, vp, i32]
@@ -159,6 +160,15 @@ def pn_accel(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None, ac
     return _check(load().pn_accel(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c, eps,
                                   precision, _ptr(acc_newton, 3 * n), _ptr(phi, n),
                                   _ptr(acc_1pn, 3 * n), _stream(stream), flags), "pn_accel")
+
+
+def pn_accel_noalloc(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None,
+                     acc_1pn=None, stream=None, flags=0):
+    n = _n(mass)
+    return _check(load().pn_accel_noalloc(_ptr(pos, 3 * n), _ptr(vel, 3 * n), _ptr(mass), n, G, c,
+                                          eps, precision, _ptr(acc_newton, 3 * n), _ptr(phi, n),
+                                          _ptr(acc_1pn, 3 * n), _stream(stream), flags),
+                  "pn_accel_noalloc")
 
 
 def pn_accel_eih(pos, vel, mass, G, c, eps, precision, acc_newton=None, phi=None, acc_1pn=None,

@@ -21,6 +21,9 @@ using namespace pn;
 
 // ------------------------------------------------------------------ errors
 char g_err[512] = "no error";
+// detail of this thread's last PN_EINVAL that has one ("" if none); per
+// thread because argument checks run before the library lock is taken
+thread_local char g_inval[256] = "";
 std::mutex g_mu;  // serialises every entry point (scratch and graphs are shared)
 
 int fail_hip(hipError_t e, const char* what, int line) {
@@ -32,6 +35,11 @@ int fail_hip(hipError_t e, const char* what, int line) {
     hipError_t e_ = (x);                                           \
     if (e_ != hipSuccess) return fail_hip(e_, #x, __LINE__);       \
   } while (0)
+
+int fail_inval(const char* what) {
+  snprintf(g_inval, sizeof g_inval, "%s", what);
+  return PN_EINVAL;
+}
 
 // ------------------------------------------------------------------ launch shapes
 struct Shape {
@@ -86,6 +94,14 @@ Shape pick_shape(int Ns, int precision) {
   }
   want_nsplit = std::max(1, std::min(want_nsplit, Ns));
   s.jchunk = (Ns + want_nsplit - 1) / want_nsplit;
+  s.nsplit = (Ns + s.jchunk - 1) / s.jchunk;
+  return s;
+}
+
+// The same shape with (at most) `want` j-splits.
+Shape with_splits(Shape s, int Ns, int want) {
+  want = std::max(1, std::min(want, Ns));
+  s.jchunk = (Ns + want - 1) / want;
   s.nsplit = (Ns + s.jchunk - 1) / s.jchunk;
   return s;
 }
@@ -148,6 +164,15 @@ Layout layout_for(int64_t N, const Shape& s, Need need) {
   return L;
 }
 
+// Scratch of pn_accel_noalloc: a file-scope device array, which the code
+// object loader places on every device the library runs on (held until the
+// process ends).  On the host the array's name is only a stand-in and is never
+// handed to a kernel or a copy: host code uses the device address that
+// hipGetSymbolAddress returns for the current device (DevState::fixed), looked
+// up once when the library first sets up that device.
+constexpr size_t kFixedScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kFixedScratchBytes];
+
 struct GraphKey {
   const void *pos = nullptr, *vel = nullptr, *mass = nullptr;
   int64_t N = 0;
@@ -183,6 +208,7 @@ struct DevState {
   hipStream_t own = nullptr;
   char* base = nullptr;
   size_t cap = 0;
+  char* fixed = nullptr;  // this device's copy of `scratch` (pn_accel_noalloc)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   GraphKey key;
@@ -211,6 +237,9 @@ int dev_state(DevState** out) {
   DevState& d = g_dev[dev];
   if (!d.init) {
     HIPCK(hipStreamCreateWithFlags(&d.own, hipStreamDefault));
+    void* fixed = nullptr;
+    HIPCK(hipGetSymbolAddress(&fixed, HIP_SYMBOL(scratch)));
+    d.fixed = static_cast<char*>(fixed);
     d.init = true;
   }
   *out = &d;
@@ -265,6 +294,7 @@ int ensure_scratch(DevState& d, size_t bytes) {
 bool dptr_ok(const void* p) { return p != nullptr && ((uintptr_t)p & 7u) == 0; }
 
 int check_system(const void* pos, const void* mass, int64_t N, double G, double c, double eps) {
+  g_inval[0] = '\0';
   if (!dptr_ok(pos) || !dptr_ok(mass)) return PN_EINVAL;
   if (N < 2 || N > ((int64_t)1 << 28)) return PN_EINVAL;
   if (!(G > 0.0) || !std::isfinite(G)) return PN_EINVAL;
@@ -722,19 +752,21 @@ int mark_call_end(DevState& d, hipStream_t st) {
   return PN_OK;
 }
 
+// Waits for st and reports the device status word of the call.
+int read_status(const Ptrs& P, hipStream_t st) {
+  int status = 0;
+  HIPCK(hipMemcpyAsync(&status, P.at<int>(P.L.status), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  if (status & 2) return fail_inval("mass[0] must be positive and finite");
+  if (status & 1) return PN_ENONFINITE;
+  return PN_OK;
+}
+
 int finish(DevState& d, const Ptrs& P, hipStream_t st, int flags) {
   int rc = mark_call_end(d, st);
   if (rc) return rc;
   if (flags & PN_ASYNC) return PN_OK;
-  int status = 0;
-  HIPCK(hipMemcpyAsync(&status, P.at<int>(P.L.status), sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  if (status & 2) {
-    snprintf(g_err, sizeof g_err, "mass[0] must be positive and finite");
-    return PN_EINVAL;
-  }
-  if (status & 1) return PN_ENONFINITE;
-  return PN_OK;
+  return read_status(P, st);
 }
 
 int reset_status(const Ptrs& P, hipStream_t st) {
@@ -1005,6 +1037,51 @@ int pn_accel(const double* pos, const double* vel, const double* mass, int64_t N
   if ((rc = enqueue_eval(s, P, sh, precision, o, st, &tm))) return rc;
   if ((rc = tm.collect((double)(N - 1) * (double)(N - 2)))) return rc;
   return finish(*d, P, st, flags & ~PN_TIMING);
+}
+
+int pn_accel_noalloc(const double* pos, const double* vel, const double* mass, int64_t N,
+                     double G, double c, double eps, int precision, double* acc_newton,
+                     double* phi, double* acc_1pn, void* stream, int flags) {
+  int rc = check_system(pos, mass, N, G, c, eps);
+  if (rc) return rc;
+  if (!dptr_ok(vel)) return PN_EINVAL;
+  if (precision != PN_FP64 && precision != PN_MIXED) return PN_EINVAL;
+  if ((acc_newton && !dptr_ok(acc_newton)) || (phi && !dptr_ok(phi)) ||
+      (acc_1pn && !dptr_ok(acc_1pn)))
+    return PN_EINVAL;
+  if (flags & PN_TIMING) return fail_inval("pn_accel_noalloc does not take PN_TIMING");
+  std::lock_guard<std::mutex> lk(g_mu);
+  // pn_accel's shape, with fewer j-splits where its partial sums would not
+  // fit the fixed scratch; sizes that do not fit even with one split are
+  // rejected before any device work
+  const int Ns = (int)(N - 1);
+  const Shape tuned = pick_shape(Ns, precision);
+  Shape sh = tuned;
+  Layout L = layout_for(N, sh, Need::EVAL);
+  for (int want = tuned.nsplit - 1; L.total > kFixedScratchBytes && want >= 1; --want) {
+    sh = with_splits(tuned, Ns, want);
+    L = layout_for(N, sh, Need::EVAL);
+  }
+  if (L.total > kFixedScratchBytes) {
+    char msg[192];
+    snprintf(msg, sizeof msg,
+             "pn_accel_noalloc: N = %lld needs %zu bytes of scratch, more than its fixed %zu",
+             (long long)N, L.total, kFixedScratchBytes);
+    return fail_inval(msg);
+  }
+  DevState* d;
+  if ((rc = dev_state(&d))) return rc;
+  Ptrs P{d->fixed, L};
+  hipStream_t st = pick_stream(*d, stream);
+  Sys s{pos, vel, mass, N, G, c, eps};
+  if ((rc = reset_status(P, st))) return rc;
+  Outs o;
+  o.acc_newton = acc_newton;
+  o.phi = phi;
+  o.acc_1pn = acc_1pn;
+  if ((rc = enqueue_eval(s, P, sh, precision, o, st, nullptr))) return rc;
+  if (flags & PN_ASYNC) return PN_OK;
+  return read_status(P, st);
 }
 
 int pn_accel_eih(const double* pos, const double* vel, const double* mass, int64_t N, double G,
@@ -1382,10 +1459,7 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
   int hstatus = 0;
   HIPCK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
-  if (hstatus & 2) {
-    snprintf(g_err, sizeof g_err, "mass of a massive object must be positive and finite");
-    return PN_EINVAL;
-  }
+  if (hstatus & 2) return fail_inval("mass of a massive object must be positive and finite");
   if (hstatus & 1) return PN_ENONFINITE;
   return PN_OK;
 }
@@ -1418,7 +1492,7 @@ int pn_query_shape(int precision, int64_t N, int* out4) {
 const char* pn_strerror(int code) {
   switch (code) {
     case PN_OK: return "ok";
-    case PN_EINVAL: return "invalid argument";
+    case PN_EINVAL: return g_inval[0] ? g_inval : "invalid argument";
     case PN_ENONFINITE: return "non-finite acceleration produced";
     case PN_EDEVICE: return g_err;
     case PN_ENOMEM: return "device allocation failed";

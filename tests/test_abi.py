@@ -99,6 +99,25 @@ def test_validation_without_device(lib):
     assert lib.pn_step_hermite(d, d, d, 1, 1.0, 30.0, 0.0, 1e-3, 1, None, 0) == EINVAL
 
 
+def test_noalloc_limits_without_device(lib):
+    """pn_accel_noalloc rejects, before any device work, a size whose scratch
+    exceeds its fixed array even with one j-split, and PN_TIMING; the error
+    text names the sizes."""
+    EINVAL = -1
+    d = FAKE
+    assert lib.pn_accel_noalloc(d, d, d, 400000, 1.0, 30.0, 0.0, 0, d, d, d, None, 0) == EINVAL
+    msg = lib.pn_strerror(EINVAL).decode()
+    assert "pn_accel_noalloc" in msg and "400000" in msg and str(64 << 20) in msg
+    assert lib.pn_accel_noalloc(d, d, d, 400000, 1.0, 30.0, 0.0, 1, d, d, d, None, 0) == EINVAL
+    assert lib.pn_accel_noalloc(d, d, d, 16, 1.0, 30.0, 0.0, 0, d, d, d, None, 4) == EINVAL
+    assert "PN_TIMING" in lib.pn_strerror(EINVAL).decode()
+    assert lib.pn_accel_noalloc(d, d, d, 16, 1.0, 30.0, 0.0, 3, d, d, d, None, 0) == EINVAL
+    assert lib.pn_accel_noalloc(d, None, d, 16, 1.0, 30.0, 0.0, 0, d, d, d, None, 0) == EINVAL
+    # a later argument error without detail does not repeat the old text
+    assert lib.pn_accel_noalloc(d, d, d, 1, 1.0, 30.0, 0.0, 0, d, d, d, None, 0) == EINVAL
+    assert lib.pn_strerror(EINVAL).decode() == "invalid argument"
+
+
 def test_batched_validation_without_device(lib):
     EINVAL = -1
     d = FAKE
