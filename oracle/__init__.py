@@ -57,6 +57,8 @@ def _load():
                           ctypes.c_double, _dp, _dp],
             "pnref_eih2": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
                            ctypes.c_double, _dp, _dp, _dp],
+            "pnref_eih2_rows": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, _i64p, _i64, _dp, _dp, _dp],
             "pnref_twobody": [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, _dp, _dp],
             "pnref_step": [_dp, _dp, _dp, _i64, ctypes.c_double, ctypes.c_double,
@@ -166,6 +168,20 @@ def eih2(pos, vel, mass, G, c, eps):
     aN, phi, a1 = np.empty((N, 3)), np.empty(N), np.empty((N, 3))
     _check(_load().pnref_eih2(_p(pos), _p(vel), _p(mass), N, G, c, eps, _p(aN), _p(phi), _p(a1)),
            "pnref_eih2")
+    return aN, phi, a1
+
+
+def eih2_rows(pos, vel, mass, G, c, eps, rows):
+    """Same as :func:`eih2` for the given body indices only (one O(N^2)
+    Newtonian pass, then O(N) per row)."""
+    N = len(mass)
+    pos, vel, mass = _arr(pos, (N, 3)), _arr(vel, (N, 3)), _arr(mass, (N,))
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    R = len(rows)
+    aN, phi, a1 = np.empty((R, 3)), np.empty(R), np.empty((R, 3))
+    _check(_load().pnref_eih2_rows(_p(pos), _p(vel), _p(mass), N, G, c, eps,
+                                   rows.ctypes.data_as(_i64p), R, _p(aN), _p(phi), _p(a1)),
+           "pnref_eih2_rows")
     return aN, phi, a1
 
 

@@ -599,6 +599,30 @@ int pnref_eih(const double *pos, const double *vel, const double *mass, idx_t N,
 /* the definition above, not regrouped.  Writes a^N, phi = -V and the   */
 /* 1PN part (times lambda) of every body.                               */
 /* ------------------------------------------------------------------ */
+/* 1PN part (without lambda) of body a from every body's Newtonian      */
+/* potential phi = -V and acceleration aN: the EIH pair sum above.      */
+static void eih_row(const double *pos, const double *vel, const double *mass, idx_t N,
+                    double G, double eps2, const double *phi, const double *acc_newton,
+                    idx_t a, double pn[3]) {
+  const double *xa = pos + 3 * a, *va = vel + 3 * a;
+  const double Va = -phi[a];
+  pn[0] = pn[1] = pn[2] = 0.0;
+  for (idx_t b = 0; b < N; ++b) {
+    if (b == a) continue;
+    const double *xb = pos + 3 * b, *vb = vel + 3 * b, *aNb = acc_newton + 3 * b;
+    double xab[3];
+    double R = sep(xa, xb, eps2, xab);
+    double n[3] = {xab[0] / R, xab[1] / R, xab[2] / R};
+    double nvb = dot3(n, vb);
+    double br = -dot3(va, va) - 2.0 * dot3(vb, vb) + 4.0 * dot3(va, vb) + 1.5 * nvb * nvb +
+                4.0 * Va - phi[b] + 0.5 * dot3(xab, aNb);
+    double D = 4.0 * dot3(n, va) - 3.0 * nvb;
+    double k = G * mass[b] / (R * R);
+    for (int q = 0; q < 3; ++q)
+      pn[q] += k * br * n[q] + k * D * (va[q] - vb[q]) + 3.5 * (G * mass[b] / R) * aNb[q];
+  }
+}
+
 int pnref_eih2(const double *pos, const double *vel, const double *mass, idx_t N, double G,
                double c, double eps, double *acc_newton, double *phi, double *acc_1pn) {
   int rc = check_common(pos, mass, N, G, eps);
@@ -610,26 +634,54 @@ int pnref_eih2(const double *pos, const double *vel, const double *mass, idx_t N
   const double eps2 = eps * eps;
 #pragma omp parallel for schedule(static)
   for (idx_t a = 0; a < N; ++a) {
-    const double *xa = pos + 3 * a, *va = vel + 3 * a;
-    const double Va = -phi[a];
-    double pn[3] = {0, 0, 0};
-    for (idx_t b = 0; b < N; ++b) {
-      if (b == a) continue;
-      const double *xb = pos + 3 * b, *vb = vel + 3 * b, *aNb = acc_newton + 3 * b;
-      double xab[3];
-      double R = sep(xa, xb, eps2, xab);
-      double n[3] = {xab[0] / R, xab[1] / R, xab[2] / R};
-      double nvb = dot3(n, vb);
-      double br = -dot3(va, va) - 2.0 * dot3(vb, vb) + 4.0 * dot3(va, vb) + 1.5 * nvb * nvb +
-                  4.0 * Va - phi[b] + 0.5 * dot3(xab, aNb);
-      double D = 4.0 * dot3(n, va) - 3.0 * nvb;
-      double k = G * mass[b] / (R * R);
-      for (int q = 0; q < 3; ++q)
-        pn[q] += k * br * n[q] + k * D * (va[q] - vb[q]) + 3.5 * (G * mass[b] / R) * aNb[q];
-    }
+    double pn[3];
+    eih_row(pos, vel, mass, N, G, eps2, phi, acc_newton, a, pn);
     for (int q = 0; q < 3; ++q) acc_1pn[3 * a + q] = lam * pn[q];
   }
   return PNREF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* pnref_eih2 for the given bodies only: the Newtonian pass over every  */
+/* body (O(N^2); every partner's potential and acceleration enters),    */
+/* then the O(N) EIH sum of each requested row.  Outputs are [nrows] /  */
+/* [nrows][3] in the order of rows.                                     */
+/* ------------------------------------------------------------------ */
+int pnref_eih2_rows(const double *pos, const double *vel, const double *mass, idx_t N,
+                    double G, double c, double eps, const idx_t *rows, idx_t nrows,
+                    double *acc_newton, double *phi, double *acc_1pn) {
+  int rc = check_common(pos, mass, N, G, eps);
+  if (rc) return rc;
+  if (check_c(c) || !vel || !rows || nrows < 0 || !acc_newton || !phi || !acc_1pn)
+    return PNREF_EINVAL;
+  for (idx_t r = 0; r < nrows; ++r)
+    if (rows[r] < 0 || rows[r] >= N) return PNREF_EINVAL;
+  double *aN = (double *)malloc(sizeof(double) * 3 * N);
+  double *ph = (double *)malloc(sizeof(double) * N);
+  if (!aN || !ph) {
+    free(aN);
+    free(ph);
+    return PNREF_ENOMEM;
+  }
+  rc = pnref_newton(pos, mass, N, G, eps, aN, ph);
+  if (!rc) {
+    const double lam = lambda_of(c);
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(static)
+    for (idx_t r = 0; r < nrows; ++r) {
+      const idx_t a = rows[r];
+      double pn[3];
+      eih_row(pos, vel, mass, N, G, eps2, ph, aN, a, pn);
+      for (int q = 0; q < 3; ++q) {
+        acc_newton[3 * r + q] = aN[3 * a + q];
+        acc_1pn[3 * r + q] = lam * pn[q];
+      }
+      phi[r] = ph[a];
+    }
+  }
+  free(aN);
+  free(ph);
+  return rc;
 }
 
 /* ------------------------------------------------------------------ */

@@ -69,6 +69,10 @@ MUTATIONS = [
      "for (int q = 0; q < 3; ++q) w[q] += mass[s] * vel[3 * s + q];"),
     ("jerk_exact_star_half_xb_sign", "u[j] - 0.5 * cdot3(d, bj);", "u[j] + 0.5 * cdot3(d, bj);"),
     ("jerk_exact_bh_Vs_sign", "4.0 * V0 + V[s] +", "4.0 * V0 - V[s] +"),
+    ("eih_row_Vb_sign", "4.0 * Va - phi[b] + 0.5 * dot3(xab, aNb);",
+     "4.0 * Va + phi[b] + 0.5 * dot3(xab, aNb);"),
+    ("eih_row_velocity_difference", "k * D * (va[q] - vb[q]) + 3.5 * (G * mass[b] / R) * aNb[q];\n  }\n}",
+     "k * D * (va[q] + vb[q]) + 3.5 * (G * mass[b] / R) * aNb[q];\n  }\n}"),
     ("jerk_exact_b_of_unperturbed_position",
      "for (int q = 0; q < 3; ++q) b[3 * s + q] = G * M * d[q] / (R * R * R);",
      "for (int q = 0; q < 3; ++q) b[3 * s + q] = G * M * creal(d[q]) / (R * R * R);"),
@@ -97,6 +101,7 @@ PIN_CALLS = [
     lambda m: pins.test_difference_quotient_converges_to_exact_jerk_as_h4(m, 3.0),
     lambda m: pins.test_jerk_exact_is_the_time_derivative_along_the_motion(m),
     lambda m: pins.test_hermite_fourth_order_with_velocity_dependent_force(m, 0.0),
+    lambda m: pins.test_eih_potentials_once_equals_brute_force(m),
 ]
 
 

@@ -387,6 +387,21 @@ def test_eih_potentials_once_equals_brute_force(oracle_mod):
         assert _rel(bN, aN) < 1e-15 and _rel(b1, a1) < 1e-14
 
 
+def test_eih_rows_equal_brute_force_and_full(oracle_mod):
+    """pnref_eih2_rows (the sampled-row form the full-size GPU tests use)
+    against the brute-force O(N^3) EIH sum on its rows, and bit for bit the
+    all-body form, massive object included."""
+    pos, vel, mass = random_cluster(14, 23, M=0.2, m_star=0.04)
+    rows = np.array([0, 13, 5, 0, 2])
+    for eps in (0.0, 3e-3):
+        aN, a1 = oracle_mod.eih(pos, vel, mass, G, 7.0, eps)
+        fN, fphi, f1 = oracle_mod.eih2(pos, vel, mass, G, 7.0, eps)
+        bN, bphi, b1 = oracle_mod.eih2_rows(pos, vel, mass, G, 7.0, eps, rows)
+        assert _rel(bN, aN[rows]) < 1e-15 and _rel(b1, a1[rows]) < 1e-14
+        assert np.array_equal(bN, fN[rows]) and np.array_equal(b1, f1[rows])
+        assert np.array_equal(bphi, fphi[rows])
+
+
 def test_eih_reduces_to_limited_form_at_first_order(oracle_mod):
     """Unrestricted minus limited is O(lm^2) in the stars' 1PN parts (the same
     truncation statement as P2, through the O(N^2) form)."""
