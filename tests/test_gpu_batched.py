@@ -144,3 +144,77 @@ def test_direct_call_of_another_ensemble_between_graph_replays(pn):
     again = step_big(0)  # same key as the cached graph
     for x, y, z in zip(ref, first, again):
         assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+@pytest.fixture(scope="module")
+def ensemble256():
+    """The benchmark's ensemble: 256 systems, N ~ U{1024..16384},
+    M ~ U[0.01, 0.1], c ~ U[20, 100], eps = 1e-4, system b seeded 10000 + b."""
+    systems = inputs.ensemble()
+    ps, vs, ms, off = [], [], [], [0]
+    for s in systems:
+        p, v, m = inputs.plummer_bh(s["N"], s["M_bh"], s["seed"])
+        ps.append(p)
+        vs.append(v)
+        ms.append(m)
+        off.append(off[-1] + s["N"])
+    return systems, np.concatenate(ps), np.concatenate(vs), np.concatenate(ms), off
+
+
+def batch_splits(Ns_all):
+    """The batched plan's j-split count of each system: a common count giving
+    the ensemble ~16k sweep workgroups (at most 16), capped so that every
+    wavefront keeps at least 32 j."""
+    tot = sum(-(-n // 64) for n in Ns_all)
+    common = max(1, min(16, -(-16384 // tot)))
+    return [max(1, min(common, n // 128)) for n in Ns_all]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_ensemble256_members_equal_pn_step(pn, ensemble256, prec):
+    """One batched RK4 step of the whole 256-system ensemble; eight members
+    (the largest, the second largest, the median, the two smallest, and three
+    seeded random ones; the largest and the smallest are the first and the
+    last in the plan's order of decreasing N) bitwise against pn_step of the
+    member alone in the batched plan's shape (1 i per lane, 4 wavefronts, the
+    plan's split count); the two smallest against the oracle's RK4 step too."""
+    from paper_1801_07986_amd import _binding
+
+    systems, pos, vel, mass, off = ensemble256
+    Ns = np.array([s["N"] for s in systems])
+    splits = batch_splits([n - 1 for n in Ns])
+    cs = [s["c"] for s in systems]
+    print(f"[case] ensemble of {len(systems)}, {off[-1]} bodies, precision {prec}, "
+          f"split counts {sorted(set(splits))}", flush=True)
+    bp, bv = run_batched(pn, pos, vel, mass, off, [(s["N"], s["M_bh"], s["c"], s["eps"], 0)
+                                                   for s in systems], 1e-4, 1, prec)
+    order = np.argsort(-Ns, kind="stable")  # the plan's order: decreasing N
+    rng = np.random.default_rng(256)
+    pick = [order[0], order[1], order[len(order) // 2], order[-2], order[-1]]
+    pick += [int(k) for k in rng.choice(np.setdiff1d(np.arange(len(systems)), pick), 3,
+                                         replace=False)]
+    worst = 0.0
+    for k in pick:
+        N, c = int(Ns[k]), cs[k]
+        sl = slice(off[k], off[k + 1])
+        print(f"[system] {k} N={N} c={c:.1f} splits={splits[k]}", flush=True)
+        pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
+        pn.pn_set_shape(prec, N, N, 1, 4, splits[k])
+        try:
+            P, V = dev(pos[sl]), dev(vel[sl])
+            pn.pn_step(P, V, dev(mass[sl]), G, c, 1e-4, 1e-4, 1, prec)
+        finally:
+            pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
+            _binding.install_tuned_shapes()
+        assert np.array_equal(bp[sl], P.cpu().numpy()) and np.array_equal(bv[sl], V.cpu().numpy())
+        if k in (order[-1], order[-2]):
+            rp, rv = oracle.step(pos[sl], vel[sl], mass[sl], G, c, 1e-4, 1e-4, 1)
+            dp = np.abs(bp[sl] - rp).max() / np.abs(rp).max()
+            dv = np.abs(bv[sl] - rv).max() / np.abs(rv).max()
+            print(f"  against the oracle: x {dp:.2e} v {dv:.2e}")
+            worst = max(worst, dp)
+            if prec == 0:
+                assert dp <= 1e-12 and dv <= 1e-12
+            else:
+                assert dp <= 1e-8 and dv <= 1e-6

@@ -1,8 +1,8 @@
 """Unrestricted EIH accelerations (pn_accel_eih) against the oracle.
 
 Tolerances as for the limited path (per-body relative error with the
-cancellation floor of test_gpu_parity): FP64 total <= 1e-12, 1PN part <= 1e-10;
-mixed total <= 1e-6, 1PN part <= 1e-4.  N = 2 with equal masses is checked
+cancellation floor of test_gpu_parity): FP64 total <= 1e-12, 1PN part <= 1e-11;
+mixed total <= 1e-6, 1PN part <= 1e-5.  N = 2 with equal masses is checked
 against the textbook two-body 1PN relative acceleration.
 """
 import numpy as np
@@ -50,11 +50,12 @@ def test_eih_parity(pn, N, prec):
     aN, phi, a1 = gpu_eih(pn, pos, vel, mass, c, eps, prec)
     rN, rphi, r1 = oracle.eih2(pos, vel, mass, G, c, eps)
     s = newton_scale(pos, mass, eps)
-    tol, tol1 = (1e-12, 1e-10) if prec == 0 else (1e-6, 1e-4)
+    tol, tol1 = (1e-12, 1e-11) if prec == 0 else (1e-6, 1e-5)
     e, e1 = body_rel(aN + a1, rN + r1, s), body_rel(a1, r1, s, 1e-6)
-    print(f"N={N} prec={prec}: total {e.max():.3e} 1PN {e1.max():.3e}")
+    ep = (np.abs(phi - rphi) / np.abs(rphi)).max()
+    print(f"N={N} prec={prec}: total {e.max():.3e} 1PN {e1.max():.3e} phi {ep:.3e}")
     assert e.max() <= tol and e1.max() <= tol1
-    assert (np.abs(phi - rphi) / np.abs(rphi)).max() <= tol
+    assert ep <= tol
 
 
 def test_eih_equal_mass_binary_is_textbook(pn):
@@ -63,5 +64,7 @@ def test_eih_equal_mass_binary_is_textbook(pn):
     mass = np.array([0.5, 0.5])
     aN, phi, a1 = gpu_eih(pn, pos, vel, mass, 6.0, 0.0, 0)
     n2, p2 = oracle.twobody(pos[1] - pos[0], vel[1] - vel[0], mass[1], mass[0], G, 6.0)
+    print(f"equal-mass binary: 1PN {np.abs((a1[1] - a1[0]) - p2).max() / np.abs(p2).max():.2e}, "
+          f"Newtonian {np.abs((aN[1] - aN[0]) - n2).max() / np.abs(n2).max():.2e}")
     assert np.abs((a1[1] - a1[0]) - p2).max() <= 1e-13 * np.abs(p2).max()
     assert np.abs((aN[1] - aN[0]) - n2).max() <= 1e-14 * np.abs(n2).max()

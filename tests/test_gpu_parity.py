@@ -1,8 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
 Tolerances (relative, per body, Euclidean norm of the 3-vector):
-  FP64 path:  total acceleration <= 1e-12, 1PN part <= 1e-10, potential <= 1e-12
-  mixed path: total acceleration <= 1e-6,  1PN part <= 1e-4
+  FP64 path:  total acceleration <= 1e-12, 1PN part <= 1e-11, potential <= 1e-12
+  mixed path: total acceleration <= 1e-6,  1PN part <= 1e-5 (N <= 2049; 3e-5
+              on the full-size systems, whose 1PN pair terms cancel more)
 The FP64 bound is the accuracy target of the method's FP64 path; the 1PN part
 is reported separately because at c = 30-50 it is only ~1e-4 of the total.
 
@@ -26,8 +27,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 G = 1.0
-TOL_FP64, TOL_FP64_1PN = 1e-12, 1e-10
-TOL_MIXED, TOL_MIXED_1PN = 1e-6, 1e-4
+TOL_FP64, TOL_FP64_1PN = 1e-12, 1e-11
+TOL_MIXED, TOL_MIXED_1PN = 1e-6, 1e-5
+# full-size mixed systems: FP32 pair terms carry ~1 ulp of the summed
+# magnitude of a body's 1PN pair terms (measured up to 1.3e-5 over all bodies
+# of the N = 65536 system against the FP64 path)
+TOL_MIXED_1PN_FULL = 3e-5
 
 
 @pytest.fixture(scope="module")
@@ -93,8 +98,10 @@ def test_potential_accel_fp64(pn, N):
     phi = torch.empty(N, dtype=torch.float64, device="cuda:0")
     pn.pn_potential_accel(dev(pos), None, dev(mass), G, 50.0, eps, aN, phi)
     rN, rphi = oracle.newton(pos, mass, G, eps)
-    assert body_rel(host(aN), rN, newton_scale(pos, mass, eps)).max() <= TOL_FP64
-    assert (np.abs(host(phi) - rphi) / np.abs(rphi)).max() <= TOL_FP64
+    e = body_rel(host(aN), rN, newton_scale(pos, mass, eps)).max()
+    ep = (np.abs(host(phi) - rphi) / np.abs(rphi)).max()
+    print(f"N={N} pn_potential_accel: max rel a^N {e:.3e}, phi {ep:.3e}")
+    assert e <= TOL_FP64 and ep <= TOL_FP64
 
 
 @pytest.mark.parametrize("N", SIZES)
@@ -105,8 +112,10 @@ def test_correction_fp64(pn, N):
     out = torch.empty((N, 3), dtype=torch.float64, device="cuda:0")
     pn.pn_correction(dev(pos), dev(vel), dev(mass), G, c, eps, dev(rphi), dev(rN), out)
     s = newton_scale(pos, mass, eps)
-    assert body_rel(host(out), r1, s, 1e-6).max() <= TOL_FP64_1PN
-    assert body_rel(rN + host(out), rN + r1, s).max() <= TOL_FP64
+    e1 = body_rel(host(out), r1, s, 1e-6).max()
+    e = body_rel(rN + host(out), rN + r1, s).max()
+    print(f"N={N} pn_correction: max rel 1PN {e1:.3e}, total {e:.3e}")
+    assert e1 <= TOL_FP64_1PN and e <= TOL_FP64
 
 
 def test_potential_then_correction_chain(pn):
@@ -122,8 +131,10 @@ def test_potential_then_correction_chain(pn):
     pn.pn_correction(P, V, Mm, G, c, eps, phi, aN, a1)
     rN, rphi, r1 = oracle.accel(pos, vel, mass, G, c, eps)
     s = newton_scale(pos, mass, eps)
-    assert body_rel(host(aN) + host(a1), rN + r1, s).max() <= TOL_FP64
-    assert body_rel(host(a1), r1, s, 1e-6).max() <= TOL_FP64_1PN
+    e = body_rel(host(aN) + host(a1), rN + r1, s).max()
+    e1 = body_rel(host(a1), r1, s, 1e-6).max()
+    print(f"chained: max rel total {e:.3e}, 1PN {e1:.3e}")
+    assert e <= TOL_FP64 and e1 <= TOL_FP64_1PN
 
 
 @pytest.mark.parametrize("N", SIZES)
@@ -147,7 +158,11 @@ def test_no_softening(pn):
     pos, vel, mass = case(300, 11)
     aN, phi, a1 = gpu_accel(pn, pos, vel, mass, 20.0, 0.0, 0)
     rN, rphi, r1 = oracle.accel(pos, vel, mass, G, 20.0, 0.0)
-    assert body_rel(aN + a1, rN + r1, newton_scale(pos, mass, 0.0)).max() <= TOL_FP64
+    s = newton_scale(pos, mass, 0.0)
+    e = body_rel(aN + a1, rN + r1, s).max()
+    e1 = body_rel(a1, r1, s, 1e-6).max()
+    print(f"eps = 0: max rel total {e:.3e}, 1PN {e1:.3e}")
+    assert e <= TOL_FP64 and e1 <= TOL_FP64_1PN
 
 
 def test_newtonian_limit_exact(pn):
@@ -155,7 +170,9 @@ def test_newtonian_limit_exact(pn):
     aN, phi, a1 = gpu_accel(pn, pos, vel, mass, math.inf, 1e-4, 0)
     assert np.all(a1 == 0.0)
     rN, _ = oracle.newton(pos, mass, G, 1e-4)
-    assert body_rel(aN, rN, newton_scale(pos, mass, 1e-4)).max() <= TOL_FP64
+    e = body_rel(aN, rN, newton_scale(pos, mass, 1e-4)).max()
+    print(f"c = inf: max rel a^N {e:.3e}")
+    assert e <= TOL_FP64
 
 
 def test_deterministic(pn):
@@ -205,7 +222,13 @@ def test_strong_field_encounter(pn):
     """The regime the large workloads' plunging stars reach: a star 2 Schwarzschild
     radii (2GM/c^2 = 2.2e-4) from the massive object, moving at 0.8 c
     tangentially, inside a Plummer sphere (N = 257, M = 0.1, c = 30,
-    eps = 1e-4).  One evaluation, then 20 RK4 steps of 1e-7, against the oracle."""
+    eps = 1e-4).  One evaluation, then 20 RK4 steps of 1e-7, against the oracle.
+    The 1PN part is held to 10x the usual bound: on every distant star the
+    massive object's pair term (1/2 x_i0 . a^N_0, with a^N_0 dominated by the
+    close star) and the close star's own (-1/2 x_i1 . b_1) are each about 1e3
+    times their sum, which they nearly cancel to (the pair acts from afar as one
+    mass), so rounding of those terms is ~1e-13 of the star's 1PN part
+    (measured 1.7e-11 at worst; the total stays at 1e-13)."""
     N, M, c, eps = 257, 0.1, 30.0, 1e-4
     pos, vel, mass = case(N, 321, M)
     r_s = 2.0 * G * M / c**2
@@ -218,7 +241,7 @@ def test_strong_field_encounter(pn):
     e1 = body_rel(a1, r1, s, 1e-6)
     print(f"strong field: |a1|/|aN| of the star {np.linalg.norm(r1[1]) / np.linalg.norm(rN[1]):.3f}; "
           f"max rel total {e.max():.3e}, 1PN {e1.max():.3e}")
-    assert e.max() <= TOL_FP64 and e1.max() <= TOL_FP64_1PN
+    assert e.max() <= TOL_FP64 and e1.max() <= 10 * TOL_FP64_1PN
     P, V = dev(pos), dev(vel)
     pn.pn_step(P, V, dev(mass), G, c, eps, 1e-7, 20, 0)
     rp, rv = oracle.step(pos, vel, mass, G, c, eps, 1e-7, 20)
@@ -263,9 +286,13 @@ def test_diagnostics(pn, N):
     c, eps = 30.0, 1e-4
     got = np.array(pn.pn_diagnostics(dev(pos), dev(vel), dev(mass), G, c, eps))
     ref = oracle.diagnostics(pos, vel, mass, G, c, eps)
+    scaleP = np.abs(mass[:, None] * vel).sum()
+    print(f"N={N} diagnostics: E_N {abs(got[0] - ref[0]) / abs(ref[0]):.2e}, E_1PN "
+          f"{abs(got[1] - ref[1]) / abs(ref[1]):.2e}, P_N "
+          f"{np.abs(got[2:5] - ref[2:5]).max() / scaleP:.2e}, P_1PN "
+          f"{np.abs(got[5:8] - ref[5:8]).max() / np.abs(ref[5:8]).max():.2e}")
     assert abs(got[0] - ref[0]) <= 1e-12 * abs(ref[0])
     assert abs(got[1] - ref[1]) <= 1e-12 * abs(ref[1])
-    scaleP = np.abs(mass[:, None] * vel).sum()
     assert np.abs(got[2:5] - ref[2:5]).max() <= 1e-13 * scaleP
     assert np.abs(got[5:8] - ref[5:8]).max() <= 1e-12 * np.abs(ref[5:8]).max()
 
@@ -323,8 +350,10 @@ def test_full_size_n16384_one_step(pn):
     P, V = dev(pos), dev(vel)
     pn.pn_step(P, V, dev(mass), G, w["c"], w["eps"], w["dt"], 1, 0)
     rp, rv = oracle.step(pos, vel, mass, G, w["c"], w["eps"], w["dt"], 1)
-    assert np.abs(host(P) - rp).max() <= 1e-14 * np.abs(rp).max()
-    assert np.abs(host(V) - rv).max() <= 1e-12 * np.abs(rv).max()
+    dp = np.abs(host(P) - rp).max() / np.abs(rp).max()
+    dv = np.abs(host(V) - rv).max() / np.abs(rv).max()
+    print(f"N=16384 one step: max |dx|/max|x| {dp:.2e}, max |dv|/max|v| {dv:.2e}")
+    assert dp <= 1e-14 and dv <= 1e-12
 
 
 def test_full_size_n65536_mixed(pn):
@@ -339,22 +368,25 @@ def test_full_size_n65536_mixed(pn):
     e = body_rel(aN[rows] + a1[rows], rN + r1, s)
     e1 = body_rel(a1[rows], r1, s, 1e-6)
     print(f"N=65536 mixed: max rel total {e.max():.3e} median {np.median(e):.3e}, "
-          f"1PN max {e1.max():.3e}")
-    assert e.max() <= TOL_MIXED and e1.max() <= TOL_MIXED_1PN
+          f"1PN max {e1.max():.3e}; massive object total {e[0]:.3e} 1PN {e1[0]:.3e}")
+    assert e.max() <= TOL_MIXED and e1.max() <= TOL_MIXED_1PN_FULL
 
 
+@pytest.mark.timeout(400)
 def test_full_size_n262144_mixed(pn):
     """N = 262144 Plummer (M = 0.1, c = 30, eps = 1e-4), the largest single
-    system, mixed precision in its tuned launch shape: the 63 stars nearest to
-    the massive object and 448 random stars against the oracle row by row (a
-    star row costs the oracle O(N); the massive object's 1PN row would need
-    every star's sums, O(N^2)), and the massive object's Newtonian row through
-    Newtonian momentum conservation, sum_a m_a a^N_a = 0."""
+    system, mixed precision in its tuned launch shape: the massive object, the
+    63 stars nearest to it and 448 random stars against the oracle row by row.
+    The massive object's 1PN row needs every star's Newtonian potential and
+    acceleration, so the oracle first runs one O(N^2) Newtonian pass (about
+    half a minute on 16 cores).  Newtonian momentum conservation,
+    sum_a m_a a^N_a = 0, is checked over all bodies as well."""
     w = inputs.WORKLOADS["plummer_n262144_mixed"]
     pos, vel, mass = inputs.plummer_bh(w["N"], w["M_bh"], w["seed"])
     print(f"[case] N={w['N']} mixed, shape {pn.pn_query_shape(1, w['N'])}", flush=True)
     aN, phi, a1 = gpu_accel(pn, pos, vel, mass, w["c"], w["eps"], 1)
-    rows = _sample_rows(pos, 63, 448, 3)[1:]
+    rows = _sample_rows(pos, 63, 448, 3)
+    print(f"[case] N={w['N']} oracle rows (massive object included)", flush=True)
     rN, rphi, r1 = oracle.accel_rows(pos, vel, mass, G, w["c"], w["eps"], rows)
     s = newton_scale(pos, mass, w["eps"], rows, chunk=32)
     e = body_rel(aN[rows] + a1[rows], rN + r1, s)
@@ -362,8 +394,9 @@ def test_full_size_n262144_mixed(pn):
     mom = np.abs((mass[:, None] * aN).sum(0)).max()
     mom_scale = np.linalg.norm(mass[:, None] * aN, axis=1).sum()
     print(f"N=262144 mixed: max rel total {e.max():.3e} median {np.median(e):.3e}, "
-          f"1PN max {e1.max():.3e}; |sum m a^N| / sum |m a^N| {mom / mom_scale:.2e}")
-    assert e.max() <= TOL_MIXED and e1.max() <= TOL_MIXED_1PN
+          f"1PN max {e1.max():.3e}; massive object total {e[0]:.3e} 1PN {e1[0]:.3e}; "
+          f"|sum m a^N| / sum |m a^N| {mom / mom_scale:.2e}")
+    assert e.max() <= TOL_MIXED and e1.max() <= TOL_MIXED_1PN_FULL
     assert mom <= 1e-6 * mom_scale
 
 

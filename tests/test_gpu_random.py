@@ -9,7 +9,7 @@ the massive object).  |a^1PN|/|a^N| reaches 115 in these draws.  Bounds as in
 the fixed-size parity tests, with the per-body floor (1e-3 of the summed
 Newtonian term magnitude) scaled by 1 + 10 lambda (v_max^2 + max potential),
 the size of what the 1PN brackets multiply: FP64 total 1e-12,
-1PN part 1e-10 (floor 1e-6), mixed total 1e-5; unrestricted EIH 1e-12 on the
+1PN part 1e-11 (floor 1e-6), mixed total 1e-5; unrestricted EIH 1e-12 on the
 total; three RK4 steps 1e-12; the jerk at c = inf against its closed form
 1e-12; Eq. (7)-(8) diagnostics 1e-12.  The mixed bound is 10x the workload
 tests' 1e-6 because at c = 1 the 1PN sums, evaluated in FP32 (2^-24 per
@@ -103,8 +103,9 @@ def test_random_system(pn, k):
 
     rN, rphi, r1 = oracle.accel(pos, vel, mass, G, c, eps)
     pn.pn_accel(P, V, Mm, G, c, eps, pn.PN_FP64, aN, phi, a1)
-    assert rel(host(aN) + host(a1), rN + r1, s) <= 1e-12
-    assert rel(host(a1), r1, s, 1e-6) <= 1e-10
+    et, e1 = rel(host(aN) + host(a1), rN + r1, s), rel(host(a1), r1, s, 1e-6)
+    print(f"fp64 total {et:.2e} 1PN {e1:.2e}")
+    assert et <= 1e-12 and e1 <= 1e-11
     assert np.abs(host(phi) - rphi).max() <= 1e-12 * np.abs(rphi).max()
 
     pn.pn_accel(P, V, Mm, G, c, eps, pn.PN_MIXED, aN, phi, a1)
@@ -114,7 +115,9 @@ def test_random_system(pn, k):
 
     eN, _, e1 = oracle.eih2(pos, vel, mass, G, c, eps)
     pn.pn_accel_eih(P, V, Mm, G, c, eps, pn.PN_FP64, aN, phi, a1)
-    assert rel(host(aN) + host(a1), eN + e1, s) <= 1e-12
+    ee = rel(host(aN) + host(a1), eN + e1, s)
+    print(f"eih fp64 total {ee:.2e}")
+    assert ee <= 1e-12
 
     d = np.array(pn.pn_diagnostics(P, V, Mm, G, c, eps))
     rd = oracle.diagnostics(pos, vel, mass, G, c, eps)
@@ -144,4 +147,6 @@ def test_random_newtonian_jerk(pn, k):
     ref = -(G * mass[None, :, None] * (dv / R3[..., None]
                                        - 3.0 * (xv / (R3 * R2))[..., None] * d)).sum(1)
     sj = (G * mass[None, :] * np.linalg.norm(dv, axis=-1) / R3).sum(1)
-    assert rel(host(jerk), ref, sj) <= 1e-12
+    ej = rel(host(jerk), ref, sj)
+    print(f"newtonian jerk {ej:.2e}")
+    assert ej <= 1e-12

@@ -2,7 +2,9 @@
 per lane, 1 or 4 wavefronts per i-range, the default or an odd split count,
 in both precisions.  Each shape runs one evaluation (pn_accel: k_pair) and
 three RK4 steps (pn_step: the chained k_epilogue_chain / k_pair_bh sequence)
-on a ragged N = 1000 system, against the oracle.  The tuned table only ever
+on a ragged N = 1000 system, against the oracle; in FP64 also the two-pass
+entry points (pn_potential_accel, then pn_correction on its outputs: the
+MODE_P1 and MODE_P2 sweeps).  The tuned table only ever
 picks some of these shapes, so without this the others would not run on the
 GPU.
 
@@ -70,6 +72,12 @@ def test_every_shape(pn, system, shape, prec):
         a1 = torch.empty_like(aN)
         phi = torch.empty(N, dtype=torch.float64, device="cuda:0")
         pn.pn_accel(dev(pos), dev(vel), dev(mass), G, C, EPS, prec, aN, phi, a1)
+        if prec == 0:
+            bN = torch.empty_like(aN)
+            b1 = torch.empty_like(aN)
+            bphi = torch.empty_like(phi)
+            pn.pn_potential_accel(dev(pos), None, dev(mass), G, C, EPS, bN, bphi)
+            pn.pn_correction(dev(pos), dev(vel), dev(mass), G, C, EPS, bphi, bN, b1)
         P, V = dev(pos), dev(vel)
         pn.pn_step(P, V, dev(mass), G, C, EPS, DT, 3, prec)
     finally:
@@ -81,6 +89,11 @@ def test_every_shape(pn, system, shape, prec):
     dv = (np.linalg.norm(gv - rv, axis=1) / np.linalg.norm(rv, axis=1).max()).max()
     print(f"evaluation {e:.2e}, three steps: x {dp:.2e}, v {dv:.2e}")
     if prec == 0:
+        eN = rel(bN.cpu().numpy(), rN, scale)
+        e1 = rel(b1.cpu().numpy(), r1, scale, 1e-6)
+        ephi = (np.abs(bphi.cpu().numpy() - rphi) / np.abs(rphi)).max()
+        print(f"two-pass: a^N {eN:.2e}, phi {ephi:.2e}, 1PN part {e1:.2e}")
+        assert eN <= 1e-12 and ephi <= 1e-12 and e1 <= 1e-11
         assert e <= 1e-12 and dp <= 1e-12 and dv <= 1e-12
     else:
         assert e <= 1e-6 and dp <= 1e-8 and dv <= 1e-6
