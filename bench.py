@@ -29,9 +29,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic flops per star-star pair interaction of the fused Newtonian +
-# 1PN sweep (add/sub/mul = 1, FMA = 2, rsqrt = 1; the Newton-type correction
-# of the FP64 reciprocal square root is overhead and not counted).
-FLOP_PER_PAIR_FUSED = 74.0
+# 1PN sweep, counted on the expression tree the sweep evaluates (add/sub/mul
+# = 1, FMA = 2, rsqrt = 1; the refinement of the FP64 reciprocal square root
+# is overhead and not counted):
+#   potential + Newtonian pull: x_ij 3 sub; R^2 3 FMA; rsqrt; R^-2, G m R^-1,
+#     G m R^-3 3 mul; U += 1 add; G += 3 FMA                          -> 20
+#   1PN pair sum: x.s_j 1 mul + 2 FMA; (x.s_j) R^-1 1 mul; S' 7 FMA (the
+#     square, 4 v_i.v_j, x.b_j/2); x.k_i 1 mul + 2 FMA; D' 1 FMA; the two
+#     coefficients 2 mul; Q += 6 FMA; sum of D' coefficients 1 add;
+#     Q7 += 3 FMA                                                     -> 48
+FLOP_PER_PAIR_FUSED = 68.0
 PEAK_FP64_VALU = 78.6e12  # 256 CUs x 2.4 GHz x 64 FMA lanes x 2 flop
 # The mixed sweep uses no packed FP32, yet measurably issues faster than the
 # FP64 one (above 78.6 TFLOP/s-equivalent), so it is held to the FP32 vector

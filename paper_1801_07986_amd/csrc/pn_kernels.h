@@ -85,15 +85,27 @@ template <> struct PkOf<float> { using type = PkF32; };
 
 // ---------------------------------------------------------------------------
 // Reciprocal square root in FP64.  The hardware estimate (v_rsq_f64) is good
-// to about 2^-24 relative; one step of the third-order series
+// to about 2^-24 relative (measured: 5.2e-8 at worst); one step of the
+// third-order series
 //   1/sqrt(x) = y (1 - r)^(-1/2) = y (1 + r/2 + 3 r^2/8 + ...),  r = 1 - x y^2
-// brings it to full double precision (residual ~ (5/16) r^3 < 2^-70).
+// brings it to full double precision (residual ~ (5/16) r^3 < 2^-70).  The
+// O(N) kernels (massive-object terms, epilogues) use this.
+//
+// The O(N^2) pair sweeps use one Newton step instead, one instruction less
+// per pair: y (1 + e) becomes y (1 + r/2) = y (1 - 3/2 e^2 - e^3/2), at most
+// 4.1e-15 below the true value (the sweep's accuracy target is 1e-12;
+// measured per-body errors stay at 1e-14).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double rsqrt_f64(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double r = fma(-x * y, y, 1.0);
   double p = fma(0.375, r, 0.5);
   return fma(y * r, p, y);
+}
+__device__ __forceinline__ double rsqrt_f64_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double r = fma(-x * y, y, 1.0);
+  return fma(y * r, 0.5, y);
 }
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt_f64(x); }
@@ -147,6 +159,13 @@ struct Dual {
 // d(x^-1/2) = -x^-3/2 dx / 2
 __device__ __forceinline__ Dual rsqrt_t(Dual x) {
   const double y = rsqrt_f64(x.v);
+  return {y, -0.5 * y * y * y * x.d};
+}
+// the pair sweep's reciprocal square root (FP64: one Newton step, see rsqrt_f64)
+__device__ __forceinline__ float rsqrt_pair(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_pair(double x) { return rsqrt_f64_newton(x); }
+__device__ __forceinline__ Dual rsqrt_pair(Dual x) {
+  const double y = rsqrt_f64_newton(x.v);
   return {y, -0.5 * y * y * y * x.d};
 }
 __device__ __forceinline__ Dual fma_uniform_c(Dual a, Dual b, Dual c) { return fma(a, b, c); }
@@ -241,20 +260,31 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 
 // Sum of `rows` partial rows of width `stride` (first K columns), fixed order:
 // thread t sums rows t, t+kBlock, ..., then a tree.  Same result in every block.
+// Split in two so that a kernel can request the rows of several sums before
+// waiting for any: rows_load (this thread's partial sums), then rows_sum.
 template <int K>
-__device__ __forceinline__ void reduce_rows(const double* part, int rows, int stride,
-                                            double* lds, double (&out)[K]) {
-  double v[K];
+__device__ __forceinline__ void rows_load(const double* part, int rows, int stride,
+                                          double (&v)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = 0.0;
   for (int r = threadIdx.x; r < rows; r += kBlock) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += part[(size_t)r * stride + k];
   }
+}
+template <int K>
+__device__ __forceinline__ void rows_sum(const double (&v)[K], double* lds, double (&out)[K]) {
   block_sum<K>(v, lds);
 #pragma unroll
   for (int k = 0; k < K; ++k) out[k] = lds[k * kBlock];
   __syncthreads();
+}
+template <int K>
+__device__ __forceinline__ void reduce_rows(const double* part, int rows, int stride,
+                                            double* lds, double (&out)[K]) {
+  double v[K];
+  rows_load<K>(part, rows, stride, v);
+  rows_sum<K>(v, lds, out);
 }
 
 __global__ void k_reset_status(int* status) {
@@ -420,7 +450,7 @@ __device__ __forceinline__ void pair_one(const typename PkOf<T>::type& p, int j,
 #pragma unroll
   for (int ii = 0; ii < IPT; ++ii) {
     const T dx = (T)(I.x[ii] - xj), dy = (T)(I.y[ii] - yj), dz = (T)(I.z[ii] - zj);
-    T rinv = rsqrt_t(fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2))));
+    T rinv = rsqrt_pair(fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2))));
     if (MASK) rinv = (j == I.idx[ii]) ? T(0) : rinv;
     const T rinv2 = rinv * rinv;
     const T mr = gm * rinv;
@@ -697,23 +727,47 @@ __device__ __forceinline__ double rk4_next(int stage, double dt, double Y, doubl
       return Y + dt / 6.0 * (K + k);
   }
 }
+// A kernel-argument pointer the compiler may not trace back to its field:
+// otherwise it merges stores through X or Xs into one store through a pointer
+// selected from a copy of the arguments in scratch memory.
+__device__ __forceinline__ double* uniform_ptr(double* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// The step-start state (X, V) and the accumulated stage sums (KX, KV) of one
+// body component, read ahead of their use (a kernel requests all its global
+// reads up front so that their latencies overlap).
+struct Rk4In {
+  double X = 0.0, V = 0.0, KX = 0.0, KV = 0.0;
+};
+__device__ __forceinline__ Rk4In rk4_load(const EpiArgs& a, size_t o) {
+  Rk4In r;
+  if (a.stage < 0 || a.stage > 3) return r;
+  r.X = a.X[o];
+  r.V = a.V[o];
+  if (a.stage > 0) {
+    r.KX = a.KX[o];
+    r.KV = a.KV[o];
+  }
+  return r;
+}
 // xv: velocity of the evaluation state (the position derivative k_x); returns
 // the next evaluation state's position and velocity component in xn, vn.
-__device__ __forceinline__ void rk4_update(const EpiArgs& a, size_t o, double xv, double acc,
-                                           double& xn, double& vn) {
+__device__ __forceinline__ void rk4_update(const EpiArgs& a, size_t o, const Rk4In& in,
+                                           double xv, double acc, double& xn, double& vn) {
   if (a.stage < 0 || a.stage > 3) return;
-  const double KX = a.stage == 0 ? 0.0 : a.KX[o];
-  const double KV = a.stage == 0 ? 0.0 : a.KV[o];
-  xn = rk4_next(a.stage, a.dt, a.X[o], KX, xv);
-  vn = rk4_next(a.stage, a.dt, a.V[o], KV, acc);
+  const double KX = in.KX, KV = in.KV;
+  xn = rk4_next(a.stage, a.dt, in.X, KX, xv);
+  vn = rk4_next(a.stage, a.dt, in.V, KV, acc);
   if (a.stage < 3) {
     a.KX[o] = a.stage == 0 ? xv : KX + 2.0 * xv;
     a.KV[o] = a.stage == 0 ? acc : KV + 2.0 * acc;
-    a.Xs[o] = xn;
-    a.Vs[o] = vn;
+    uniform_ptr(a.Xs)[o] = xn;
+    uniform_ptr(a.Vs)[o] = vn;
   } else {
-    a.X[o] = xn;
-    a.V[o] = vn;
+    uniform_ptr(a.X)[o] = xn;
+    uniform_ptr(a.V)[o] = vn;
   }
 }
 
@@ -753,11 +807,16 @@ __device__ __forceinline__ void hermite_update(const EpiArgs& a, size_t o, doubl
 // The massive object's acceleration A0 = a^N_0, potential magnitude V0 = -phi_0
 // and the star momentum P, from the prologue partials (or the caller's inputs).
 template <typename S>
-__device__ __forceinline__ void bh_quantities(const EpiArgs& a, double* lds, S (&A0)[3], S& V0,
-                                              S (&P)[3]) {
-  constexpr int K = IsDual<S>::value ? 16 : 7;  // columns read per prologue row
+constexpr int bh_cols() { return IsDual<S>::value ? 16 : 7; }  // columns read per prologue row
+
+// rows: this thread's partial sums of the prologue rows (rows_load)
+template <typename S>
+__device__ __forceinline__ void bh_quantities(const EpiArgs& a, double* lds,
+                                              const double (&rows)[bh_cols<S>()], S (&A0)[3],
+                                              S& V0, S (&P)[3]) {
+  constexpr int K = bh_cols<S>();
   double r[K];
-  reduce_rows<K>(a.bpart, a.nbpro, IsDual<S>::value ? 16 : 8, lds, r);
+  rows_sum<K>(rows, lds, r);
   const double M = a.mass[0];
   A0[0] = get<S>(r, 0, 8) / M;
   A0[1] = get<S>(r, 1, 8) / M;
@@ -798,61 +857,121 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   constexpr bool DUAL = IsDual<S>::value;
   constexpr int W = DUAL ? 2 : 1;
   constexpr int NFO = kNF * W;
-  S A0[3], V0, P[3];
-  bh_quantities<S>(a, lds, A0, V0, P);
+  // Every global read of the workgroup is requested before the first wait:
+  // the prologue rows, the pair partials, the star's own inputs and Runge-Kutta
+  // state, the massive object's state.  (At small N this kernel is a chain of
+  // memory latencies; issued in order, they added up.)
+  double rows[bh_cols<S>()];
+  rows_load<bh_cols<S>()>(a.bpart, a.nbpro, DUAL ? 16 : 8, rows);
   const double M = a.mass[0];
-  const double gM = a.G * M;
-  const S w[3] = {-P[0] / M, -P[1] / M, -P[2] / M};
   const S x0 = ld<S>(a.pos, a.pos_d, 0), y0 = ld<S>(a.pos, a.pos_d, 1),
           z0 = ld<S>(a.pos, a.pos_d, 2);
-
-  // split reduction: thread (g, l) sums fields g, g+4, g+8, ... of star l, in
-  // split order; the loads of 16 (then 8) splits are issued together (one
-  // memory latency per batch instead of one per split), then added in order
-  {
-    const int g = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int k = blk * kEpiStars + l;
-    if (k < a.Ns) {
-      const size_t plane = (size_t)a.Ns;
-      const size_t sstride = (size_t)NFO * plane;
-      for (int f = g; f < NFO; f += 4) {
-        double sum = 0.0;
-        if (epi_field_used(f, a)) {
-          const double* src = a.part + (size_t)f * plane + k;
-          int sp = 0;
-          for (; sp + 16 <= a.nsplit; sp += 16) {
-            double v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = src[(size_t)(sp + q) * sstride];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) sum += v[q];
-          }
-          for (; sp + 8 <= a.nsplit; sp += 8) {
-            double v[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = src[(size_t)(sp + q) * sstride];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) sum += v[q];
-          }
-          for (; sp < a.nsplit; ++sp) sum += src[(size_t)sp * sstride];
-        }
-        fsum[f * kEpiStars + l] = sum;
+  const int k = blk * kEpiStars + threadIdx.x;
+  const bool star = threadIdx.x < kEpiStars && k < a.Ns;
+  const int i = k + 1;
+  S ui = 0.0, bx = 0.0, by = 0.0, bz = 0.0, xi = 0.0, yi = 0.0, zi = 0.0;
+  S vi[3] = {0.0, 0.0, 0.0};
+  double gm_s = 0.0;
+  Rk4In rk[3];
+  // the massive object's step-start position, stage sum and velocity (uniform:
+  // scalar loads)
+  double bh_x[3] = {0.0, 0.0, 0.0}, bh_kx[3] = {0.0, 0.0, 0.0}, bh_v[3] = {0.0, 0.0, 0.0};
+  if constexpr (!DUAL && !std::is_void<PkT>::value) {
+    if (a.stage >= 0) {
+      for (int c = 0; c < 3; ++c) {
+        bh_x[c] = a.X[c];
+        bh_kx[c] = a.stage == 0 ? 0.0 : a.KX[c];
+        bh_v[c] = a.vel[c];
       }
     }
   }
-  __syncthreads();
+  if (star) {
+    const double* ub = a.ub + 4 * W * (size_t)k;
+    ui = get<S>(ub, 0, 4);
+    bx = get<S>(ub, 1, 4);
+    by = get<S>(ub, 2, 4);
+    bz = get<S>(ub, 3, 4);
+    xi = ld<S>(a.pos, a.pos_d, 3 * i);
+    yi = ld<S>(a.pos, a.pos_d, 3 * i + 1);
+    zi = ld<S>(a.pos, a.pos_d, 3 * i + 2);
+    if (!a.newton_only) {
+      vi[0] = ld<S>(a.vel, a.vel_d, 3 * i);
+      vi[1] = ld<S>(a.vel, a.vel_d, 3 * i + 1);
+      vi[2] = ld<S>(a.vel, a.vel_d, 3 * i + 2);
+      gm_s = a.G * a.mass[i];
+    }
+    if constexpr (!DUAL) {
+      for (int c = 0; c < 3; ++c) rk[c] = rk4_load(a, 3 * (size_t)i + c);
+    }
+  }
+
+  // split reduction: thread (g, l) sums fields g, g+4, g+8, ... of star l, in
+  // split order; the loads of up to 8 (dual: 4) splits of all its fields are
+  // issued together, then added in order
+  {
+    constexpr int FPT = (NFO + 3) / 4;      // fields per thread
+    constexpr int BATCH = DUAL ? 4 : 8;     // splits per batch of loads
+    const int g = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int kk = blk * kEpiStars + l;
+    if (kk < a.Ns) {
+      const size_t plane = (size_t)a.Ns;
+      const size_t sstride = (size_t)NFO * plane;
+      double sum[FPT];
+      bool use[FPT];
+#pragma unroll
+      for (int fi = 0; fi < FPT; ++fi) {
+        const int f = g + 4 * fi;
+        sum[fi] = 0.0;
+        use[fi] = f < NFO && epi_field_used(f, a);
+      }
+      const double* src = a.part + (size_t)g * plane + kk;
+      int sp = 0;
+      for (; sp + BATCH <= a.nsplit; sp += BATCH) {
+        double v[FPT][BATCH];
+#pragma unroll
+        for (int fi = 0; fi < FPT; ++fi)
+#pragma unroll
+          for (int q = 0; q < BATCH; ++q)
+            v[fi][q] = use[fi] ? src[(size_t)4 * fi * plane + (size_t)(sp + q) * sstride] : 0.0;
+#pragma unroll
+        for (int fi = 0; fi < FPT; ++fi)
+#pragma unroll
+          for (int q = 0; q < BATCH; ++q) sum[fi] += v[fi][q];
+      }
+      if (sp < a.nsplit) {  // the remaining splits, also in one batch
+        double v[FPT][BATCH];
+#pragma unroll
+        for (int fi = 0; fi < FPT; ++fi)
+#pragma unroll
+          for (int q = 0; q < BATCH; ++q)
+            v[fi][q] = (use[fi] && sp + q < a.nsplit)
+                           ? src[(size_t)4 * fi * plane + (size_t)(sp + q) * sstride]
+                           : 0.0;
+#pragma unroll
+        for (int fi = 0; fi < FPT; ++fi)
+#pragma unroll
+          for (int q = 0; q < BATCH; ++q)
+            if (sp + q < a.nsplit) sum[fi] += v[fi][q];
+      }
+#pragma unroll
+      for (int fi = 0; fi < FPT; ++fi)
+        if (g + 4 * fi < NFO) fsum[(g + 4 * fi) * kEpiStars + l] = sum[fi];
+    }
+  }
+  S A0[3], V0, P[3];
+  bh_quantities<S>(a, lds, rows, A0, V0, P);  // (its first barrier also orders fsum)
+  const double gM = a.G * M;
+  const S w[3] = {-P[0] / M, -P[1] / M, -P[2] / M};
 
   constexpr bool CHAIN = !std::is_void<PkT>::value;
   constexpr bool JNEXT = std::is_same<PkT, Dual>::value;  // the jerk sweep's packets
   constexpr int NP = JNEXT ? 14 : 7;  // block-sum terms of the next prologue
   static_assert(!CHAIN || !DUAL, "chained epilogues are FP64 evaluations");
-  const int k = blk * kEpiStars + threadIdx.x;
   S bh[3] = {0.0, 0.0, 0.0};
   double pro[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) pro[q] = 0.0;
-  if (threadIdx.x < kEpiStars && k < a.Ns) {
-    const int i = k + 1;
+  if (star) {
     const int t = threadIdx.x;
     S sum[kNF];
 #pragma unroll
@@ -861,20 +980,11 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
       else sum[f] = fsum[f * kEpiStars + t];
     }
     sum[F_C2] *= kSqrt32;  // the sweep accumulates D'/sqrt(3/2)
-    const double* ub = a.ub + 4 * W * (size_t)k;
-    const S ui = get<S>(ub, 0, 4), bx = get<S>(ub, 1, 4), by = get<S>(ub, 2, 4),
-            bz = get<S>(ub, 3, 4);
     // Newtonian part: g_i - b_i with g_i = -G_i
     const S aN[3] = {-sum[F_G] - bx, -sum[F_G + 1] - by, -sum[F_G + 2] - bz};
     S Vi = sum[F_U] + ui;  // -phi_i
     S a1[3] = {0.0, 0.0, 0.0};
-    const S xi = ld<S>(a.pos, a.pos_d, 3 * i), yi = ld<S>(a.pos, a.pos_d, 3 * i + 1),
-            zi = ld<S>(a.pos, a.pos_d, 3 * i + 2);
-    S vi[3] = {0.0, 0.0, 0.0};
     if (!a.newton_only) {
-      vi[0] = ld<S>(a.vel, a.vel_d, 3 * i);
-      vi[1] = ld<S>(a.vel, a.vel_d, 3 * i + 1);
-      vi[2] = ld<S>(a.vel, a.vel_d, 3 * i + 2);
       const S vi2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
       S Vphi = Vi;
       S aNs[3] = {aN[0], aN[1], aN[2]};
@@ -908,7 +1018,6 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
       }
       // this star's term of the massive object's 1PN sum (Eqs. (2)-(3))
       const S Vs = Vphi;
-      const double gm_s = a.G * a.mass[i];
       const S ks = gm_s * rinv0 * rinv0;
       const S n0s[3] = {-n0[0], -n0[1], -n0[2]};
       const S d0s[3] = {-d0[0], -d0[1], -d0[2]};
@@ -962,12 +1071,12 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
       }
       if (a.stage >= 0) {
         double xn[3] = {0.0, 0.0, 0.0}, vn[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < 3; ++c) rk4_update(a, 3 * (size_t)i + c, vi[c], at[c], xn[c], vn[c]);
+        for (int c = 0; c < 3; ++c)
+          rk4_update(a, 3 * (size_t)i + c, rk[c], vi[c], at[c], xn[c], vn[c]);
         if constexpr (CHAIN && !JNEXT) {
           // the massive object's next position, as k_bh_final will compute it
           double x0n[3];
-          for (int c = 0; c < 3; ++c)
-            x0n[c] = rk4_next(a.stage, a.dt, a.X[c], a.stage == 0 ? 0.0 : a.KX[c], a.vel[c]);
+          for (int c = 0; c < 3; ++c) x0n[c] = rk4_next(a.stage, a.dt, bh_x[c], bh_kx[c], bh_v[c]);
           star_terms<PkT, double>(x0n, xn, vn, a.mass[i], a.G, gM, a.eps2, a.pk_next, a.ub_next,
                                   k, pro);
         }
@@ -1019,54 +1128,50 @@ template <typename S>
 __device__ __forceinline__ void bh_final_block(const EpiArgs& a, double* lds) {
   constexpr bool DUAL = IsDual<S>::value;
   constexpr int W = DUAL ? 2 : 1;
+  // both row sets and the massive object's own state are requested before
+  // the first wait (see epilogue_block)
+  double rows[bh_cols<S>()], rows1[4 * W - 1];  // 1PN rows: columns 0..2 (4..6: derivatives)
+  rows_load<bh_cols<S>()>(a.bpart, a.nbpro, DUAL ? 16 : 8, rows);
+  if (!a.newton_only) rows_load<4 * W - 1>(a.bhpart, a.nbepi, 4 * W, rows1);
+  // thread c < 3 finishes component c: its velocity and Runge-Kutta state
+  const int cc = threadIdx.x;
+  S v0c = 0.0;
+  Rk4In rkc;
+  if (cc < 3) {
+    if (!a.newton_only) v0c = ld<S>(a.vel, a.vel_d, cc);
+    if constexpr (!DUAL) rkc = rk4_load(a, (size_t)cc);
+  }
   S A0[3], V0, P[3];
-  bh_quantities<S>(a, lds, A0, V0, P);
+  bh_quantities<S>(a, lds, rows, A0, V0, P);
   S T[3] = {0.0, 0.0, 0.0};
   if (!a.newton_only) {
-    double r[4 * W - 1];  // columns 0..2 (and 4..6: derivatives)
-    reduce_rows<4 * W - 1>(a.bhpart, a.nbepi, 4 * W, lds, r);
+    double r[4 * W - 1];
+    rows_sum<4 * W - 1>(rows1, lds, r);
     for (int c = 0; c < 3; ++c) T[c] = get<S>(r, c, 4);
   }
-  if (threadIdx.x == 0) {
-    S a1[3], at[3], v0[3] = {0.0, 0.0, 0.0};
-    for (int c = 0; c < 3; ++c) {
-      a1[c] = a.lam * T[c];
-      at[c] = A0[c] + a1[c];
-    }
-    if (!a.newton_only) {
-      v0[0] = ld<S>(a.vel, a.vel_d, 0);
-      v0[1] = ld<S>(a.vel, a.vel_d, 1);
-      v0[2] = ld<S>(a.vel, a.vel_d, 2);
-    }
-    if (a.acc_newton) {
-      a.acc_newton[0] = val(A0[0]);
-      a.acc_newton[1] = val(A0[1]);
-      a.acc_newton[2] = val(A0[2]);
-    }
-    if (a.phi) a.phi[0] = -val(V0);
-    if (a.acc_1pn) {
-      a.acc_1pn[0] = val(a1[0]);
-      a.acc_1pn[1] = val(a1[1]);
-      a.acc_1pn[2] = val(a1[2]);
-    }
-    if (a.acc_tot) {
-      for (int c = 0; c < 3; ++c) a.acc_tot[c] = val(at[c]);
-    }
-    if (!finite_s(at[0]) || !finite_s(at[1]) || !finite_s(at[2])) atomicOr(a.status, 1);
+  // component c of the massive object's outputs and update (c a constant in
+  // each call below, so that nothing is indexed at run time)
+  auto finish = [&](int c, const S& A0c, const S& Tc) {
+    const S a1c = a.lam * Tc;
+    const S atc = A0c + a1c;
+    if (a.acc_newton) a.acc_newton[c] = val(A0c);
+    if (a.phi && c == 0) a.phi[0] = -val(V0);
+    if (a.acc_1pn) a.acc_1pn[c] = val(a1c);
+    if (a.acc_tot) a.acc_tot[c] = val(atc);
+    if (!finite_s(atc)) atomicOr(a.status, 1);
     if constexpr (DUAL) {
-      if (a.jerk) {
-        for (int c = 0; c < 3; ++c) a.jerk[c] = at[c].d;
-      }
-      if (a.herm >= 0) {
-        for (int c = 0; c < 3; ++c) hermite_update(a, (size_t)c, at[c].v, at[c].d);
-      }
+      if (a.jerk) a.jerk[c] = atc.d;
+      if (a.herm >= 0) hermite_update(a, (size_t)c, atc.v, atc.d);
     } else {
       if (a.stage >= 0) {
         double xn, vn;
-        for (int c = 0; c < 3; ++c) rk4_update(a, (size_t)c, v0[c], at[c], xn, vn);
+        rk4_update(a, (size_t)c, rkc, v0c, atc, xn, vn);
       }
     }
-  }
+  };
+  if (cc == 0) finish(0, A0[0], T[0]);
+  else if (cc == 1) finish(1, A0[1], T[1]);
+  else if (cc == 2) finish(2, A0[2], T[2]);
 }
 
 template <typename S>
