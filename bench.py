@@ -51,10 +51,10 @@ PEAK_FP32_VALU = 157.3e12
 # Keyed by (workload, kernel, j-splits): the launch shape comes from the tuned
 # table, so a figure applies only to the kernel and split count it was taken on.
 TRAFFIC_BYTES = {
-    # FETCH 6315.5 KiB, WRITE 46109.4 KiB per launch
-    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,4>", 32): 60150170,
-    # FETCH 64259.4 KiB, WRITE 141502.1 KiB per launch
-    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 24): 276501402,
+    # FETCH 6308.74 KiB, WRITE 46109.4 KiB per launch
+    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,4>", 32): 60136327,
+    # FETCH 64258.3 KiB, WRITE 141502.0 KiB per launch
+    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 24): 276499046,
 }
 
 
@@ -419,13 +419,43 @@ PAPER_TABLE32 = {100: (1.5392, 0.1299, 0.3479, 0.0043), 300: (1.9651, 0.1308, 3.
                  10000: (38.934, 0.0100, 3358.6, 2.1313), 30000: (339.956, 0.1391, 30188, 17.482)}
 
 
-def table32(pn, torch, inputs, samples, with_cpu):
+def oracle_table32(oracle, pos0, vel0, mass0, samples, budget_s):
+    """The oracle under the Table 3.2 protocol (energy, 32 RK4 steps of 2^-17,
+    energy; its own RK4, four force evaluations per step): as many of
+    `samples` runs as fit in budget_s (mean, standard deviation); when not
+    even one fits, 128 evaluations + 2 energies scaled from one of each,
+    labelled extrapolated."""
+    dt = 2.0 ** -17
+    t0 = time.perf_counter()
+    oracle.accel(pos0, vel0, mass0, 1.0, 1.0, 1e-3)
+    t_eval = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.diagnostics(pos0, vel0, mass0, 1.0, 1.0, 1e-3)
+    t_en = time.perf_counter() - t0
+    est = 128 * t_eval + 2 * t_en
+    k = int(min(samples, budget_s // est))
+    if k < 1:
+        return {"mean_s": est, "std_s": None, "runs": 0,
+                "kind": "extrapolated: 128 x one force evaluation + 2 x one energy"}
+    times = []
+    for _ in range(k):
+        t0 = time.perf_counter()
+        oracle.diagnostics(pos0, vel0, mass0, 1.0, 1.0, 1e-3)
+        oracle.step(pos0, vel0, mass0, 1.0, 1.0, 1e-3, dt, 32)
+        oracle.diagnostics(pos0, vel0, mass0, 1.0, 1.0, 1e-3)
+        times.append(time.perf_counter() - t0)
+    return {"mean_s": float(np.mean(times)), "std_s": float(np.std(times)), "runs": k,
+            "kind": f"measured: the protocol run {k} time(s)"}
+
+
+def table32(pn, torch, inputs, samples, with_cpu, oracle_budget_s=40.0):
     """Table 3.2 protocol on this GPU: for each N, `samples` runs of (energy,
     32 RK4 steps, energy) on the paper's test model (cold shell 1 < r < 10,
     M = 100 m, c = G = 1, eps = 1e-3, dt = 2^-17), wall time from inputs on the
     GPU to the final energy on the host.  CPU leg: the oracle (one thread, as
-    the paper's single core, and all threads) timed for one force evaluation
-    and one energy evaluation, scaled to 128 evaluations + 2 energies."""
+    the paper's single core, and all threads) under the same protocol, up to
+    `samples` runs within oracle_budget_s per N and thread count, else
+    extrapolated from one evaluation (see oracle_table32)."""
     import oracle
 
     rows = []
@@ -453,23 +483,18 @@ def table32(pn, torch, inputs, samples, with_cpu):
         if with_cpu:
             for label, threads in (("cpu1", 1), ("cpu_all", default_threads)):
                 oracle.set_threads(threads)
-                nthr = oracle.max_threads()
-                t0 = time.perf_counter()
-                oracle.accel(pos0, vel0, mass0, 1.0, 1.0, 1e-3)
-                t_eval = time.perf_counter() - t0
-                t0 = time.perf_counter()
-                oracle.diagnostics(pos0, vel0, mass0, 1.0, 1.0, 1e-3)
-                t_en = time.perf_counter() - t0
-                row[f"oracle_{label}_s"] = 128 * t_eval + 2 * t_en
-                row[f"oracle_{label}_threads"] = nthr
-                log(f"table32 N={N} oracle {label}: {row[f'oracle_{label}_s']:.2f} s "
-                    f"(extrapolated from one evaluation)")
+                r = oracle_table32(oracle, pos0, vel0, mass0, samples, oracle_budget_s)
+                r["threads"] = oracle.max_threads()
+                row[f"oracle_{label}"] = r
+                log(f"table32 N={N} oracle {label} ({r['threads']} threads): {r['mean_s']:.3f} s "
+                    f"({r['kind']})")
+            oracle.set_threads(default_threads)
         rows.append(row)
         log(f"table32 N={N}: GPU {row['gpu_mean_s'] * 1e3:.2f} +- {row['gpu_std_s'] * 1e3:.2f} ms "
             f"(paper K20c {paper[0]} s, paper 1 core {paper[2]} s)")
     return {"protocol": "Table 3.2: 32 RK4 steps + energy at start and end", "samples": samples,
             "initial_conditions": "cold shell 1<r<10, M=100m, c=G=1, eps=1e-3, dt=2^-17",
-            "rows": rows}
+            "oracle_budget_s_per_N_and_thread_count": oracle_budget_s, "rows": rows}
 
 
 def cpu_baseline(pos, vel, mass, G, c, eps, budget_s=12.0):

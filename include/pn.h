@@ -230,6 +230,23 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
                     int64_t nsteps, int precision, void* stream, int flags);
 
 /*
+ * Sweep shape of pn_step_batched in the given precision (searched by the
+ * autotuner over whole ensemble steps): ipt i-bodies per lane (1 or 2) for
+ * every system, and the ensemble's common j-split count (1..64; 0 = the
+ * default rule, about 16k sweep workgroups in all), which each system caps so
+ * that a wavefront keeps at least 32 j.  precision < 0 restores the defaults
+ * (1 i per lane, the rule).  Like pn_set_shape, it changes speed only.
+ */
+int pn_set_batch_shape(int precision, int ipt, int nsplit);
+
+/*
+ * The shape pn_step_batched would use for this ensemble (HOST offsets as
+ * pn_step_batched takes them): out (HOST, n_sys + 1 ints) = [i-bodies per
+ * lane, then each system's j-split count].  Host only.
+ */
+int pn_query_batch_shape(int precision, int32_t n_sys, const int64_t* offsets, int* out);
+
+/*
  * Launch shape of the star-star sweep for systems with n_min <= N <= n_max in
  * the given precision (searched by the autotuner; later entries never override
  * earlier ones that match).  ipt: i-bodies per lane (1 or 2); ws: wavefronts

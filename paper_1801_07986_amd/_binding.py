@@ -20,7 +20,8 @@ PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
 
 EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
            "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape",
-           "pn_accel_eih", "pn_encounters", "pn_jerk", "pn_step_hermite", "pn_query_shape", "pn_accel_noalloc")
+           "pn_accel_eih", "pn_encounters", "pn_jerk", "pn_step_hermite", "pn_query_shape", "pn_accel_noalloc", "pn_set_batch_shape",
+           "pn_query_batch_shape")
 TUNED_PATH = os.path.join(HERE, "tuned_shapes.json")
 
 
@@ -60,6 +61,8 @@ def load():
         lib.pn_release.argtypes = []
         lib.pn_set_shape.argtypes = [i32, i64, i64, i32, i32, i32]
         lib.pn_query_shape.argtypes = [i32, i64, vp]
+        lib.pn_set_batch_shape.argtypes = [i32, i32, i32]
+        lib.pn_query_batch_shape.argtypes = [i32, ctypes.c_int32, vp, vp]
         for name in EXPORTS:
             if name != "pn_strerror":
                 getattr(lib, name).restype = i32
@@ -78,11 +81,17 @@ def install_tuned_shapes(path: str | None = None) -> int:
     with open(path) as f:
         table = json.load(f)
     _lib.pn_set_shape(-1, 0, 0, 0, 0, 0)
+    _lib.pn_set_batch_shape(-1, 0, 0)
     n = 0
     for e in table.get("entries", []):
         prec = PN_MIXED if e["precision"] == "mixed" else PN_FP64
         _check(_lib.pn_set_shape(prec, int(e["n_min"]), int(e["n_max"]), int(e["ipt"]),
                                  int(e["ws"]), int(e["nsplit"])), "pn_set_shape")
+        n += 1
+    for e in table.get("batched", []):
+        prec = PN_MIXED if e["precision"] == "mixed" else PN_FP64
+        _check(_lib.pn_set_batch_shape(prec, int(e["ipt"]), int(e["nsplit"])),
+               "pn_set_batch_shape")
         n += 1
     return n
 
@@ -97,6 +106,20 @@ def pn_query_shape(precision, N):
     _check(load().pn_query_shape(precision, int(N), ctypes.cast(out, ctypes.c_void_p)),
            "pn_query_shape")
     return tuple(out)
+
+
+def pn_set_batch_shape(precision, ipt, nsplit):
+    return _check(load().pn_set_batch_shape(precision, ipt, nsplit), "pn_set_batch_shape")
+
+
+def pn_query_batch_shape(precision, offsets):
+    """(ipt, [j-splits of each system]) that pn_step_batched would use."""
+    n_sys = len(offsets) - 1
+    off = (ctypes.c_int64 * (n_sys + 1))(*[int(o) for o in offsets])
+    out = (ctypes.c_int * (n_sys + 1))()
+    _check(load().pn_query_batch_shape(precision, n_sys, ctypes.cast(off, ctypes.c_void_p),
+                                       ctypes.cast(out, ctypes.c_void_p)), "pn_query_batch_shape")
+    return out[0], list(out[1:])
 
 
 def _check(rc: int, name: str) -> int:

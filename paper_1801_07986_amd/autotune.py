@@ -19,7 +19,13 @@ the geometric midpoints between measured sizes) to ``tuned_shapes.json``,
 which the binding installs into the library with ``pn_set_shape`` when it is
 loaded.  Shapes change only the speed: every shape computes the same sums.
 
-Usage (on the GPU):  python -m paper_1801_07986_amd.autotune [--out PATH] [--quick]
+With --batched it instead tunes pn_step_batched on the benchmark's 256-system
+ensemble (N ~ U{1024..16384}): whole ensemble steps over i-bodies per lane
+(1 or 2, every system) x the common j-split count (the rule, 1, 2, 4, 8), per
+precision, and stores the fastest under "batched" in the same table
+(installed with pn_set_batch_shape).
+
+Usage (on the GPU):  python -m paper_1801_07986_amd.autotune [--out PATH] [--quick | --batched]
 """
 from __future__ import annotations
 
@@ -99,6 +105,60 @@ def tune(sizes, log=print):
     return results
 
 
+BATCH_CANDIDATES = [(ipt, ns) for ipt in (1, 2) for ns in (0, 1, 2, 4, 8)]
+
+
+def tune_batched(log=print, steps=2, reps=2):
+    """Fastest (ipt, common split count) of pn_step_batched per precision on
+    the 256-system ensemble, timing whole ensemble steps (graph replay)."""
+    import numpy as np
+    import torch
+
+    import paper_1801_07986_amd as pn
+    from paper_1801_07986_amd import inputs
+
+    pn.load()
+    systems = inputs.ensemble()
+    ps, vs, ms, off = [], [], [], [0]
+    for s in systems:
+        p, v, m = inputs.plummer_bh(s["N"], s["M_bh"], s["seed"])
+        ps.append(p)
+        vs.append(v)
+        ms.append(m)
+        off.append(off[-1] + s["N"])
+    P = torch.from_numpy(np.concatenate(ps)).cuda()
+    V = torch.from_numpy(np.concatenate(vs)).cuda()
+    Mm = torch.from_numpy(np.concatenate(ms)).cuda()
+    Gs = [1.0] * len(systems)
+    cs = [s["c"] for s in systems]
+    es = [s["eps"] for s in systems]
+    out = []
+    for prec_name, prec in (("fp64", pn.PN_FP64), ("mixed", pn.PN_MIXED)):
+        timings = {}
+        for ipt, ns in BATCH_CANDIDATES:
+            os.environ["PN_BATCH_SHAPE"] = f"{ipt},{ns}"
+            pn.pn_step_batched(off, Gs, cs, es, P, V, Mm, 1e-7, 1, prec)  # captures the graph
+            torch.cuda.synchronize()
+            best = None
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                pn.pn_step_batched(off, Gs, cs, es, P, V, Mm, 1e-7, steps, prec)
+                torch.cuda.synchronize()
+                ms_step = (time.perf_counter() - t0) / steps * 1e3
+                best = ms_step if best is None else min(best, ms_step)
+            timings[(ipt, ns)] = best
+            log(f"[autotune] ensemble {prec_name} ipt={ipt} splits={ns or 'rule'}: "
+                f"{best:.3f} ms/step")
+        os.environ.pop("PN_BATCH_SHAPE", None)
+        (ipt, ns), ms_best = min(timings.items(), key=lambda kv: kv[1])
+        out.append(dict(precision=prec_name, ipt=ipt, nsplit=ns, step_ms=round(ms_best, 4),
+                        default_step_ms=round(timings[(1, 0)], 4), n_sys=len(systems),
+                        bodies=int(off[-1])))
+        log(f"[autotune] ensemble {prec_name}: best ipt={ipt} splits={ns or 'rule'} "
+            f"{ms_best:.3f} ms/step (1 i per lane, rule: {timings[(1, 0)]:.3f})")
+    return out
+
+
 def to_table(results):
     entries = []
     for prec in ("fp64", "mixed"):
@@ -119,10 +179,23 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "tuned_shapes.json"))
     ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="tune pn_step_batched's shape only (kept with the existing table)")
     args = ap.parse_args(argv)
-    res = tune(QUICK_SIZES if args.quick else SIZES,
-               log=lambda m: print(m, file=sys.stderr, flush=True))
-    table = to_table(res)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    old = {}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            old = json.load(f)
+    if args.batched:
+        table = dict(old)
+        table["batched"] = tune_batched(log=log)
+        table["batched_created"] = time.strftime("%Y-%m-%d %H:%M:%S")
+    else:
+        table = to_table(tune(QUICK_SIZES if args.quick else SIZES, log=log))
+        if "batched" in old:
+            table["batched"] = old["batched"]
+            table["batched_created"] = old.get("batched_created")
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
         f.write("\n")

@@ -18,7 +18,12 @@ HEADERS = [os.path.join(HERE, "csrc", "pn_kernels.h"), os.path.join(ROOT, "inclu
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU
 # instructions (v_pk_fma_f32 & co.); the host pass warns that it does not know
 # the feature, which is harmless.
+# -ffp-contract=off: every fused multiply-add in the kernels is an explicit
+# fma(); the compiler may not fuse a*b + c on its own, which it otherwise
+# decides per kernel, so that one source function inlined into two kernels
+# (a single system's step and the batched step, say) rounds identically.
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-ffp-contract=off",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-function"]
 
@@ -48,7 +53,7 @@ def build(verbose: bool = False) -> str:
 def assembly(out: str) -> None:
     """Write the gfx950 assembly of the device code (for inspection)."""
     cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "--cuda-device-only", "-S",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"), "-o", out,
            *SOURCES]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL)

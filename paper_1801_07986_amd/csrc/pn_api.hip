@@ -194,12 +194,12 @@ struct BatchKey {
   const void *pos = nullptr, *vel = nullptr, *mass = nullptr;
   double dt = 0;
   int precision = -1;
-  int splits = 0;  // the plan's common split count
+  int ipt = 0, splits = 0;  // the plan's shape: i per lane, common split count
   char* base = nullptr;
   bool operator==(const BatchKey& o) const {
     return offsets == o.offsets && G == o.G && c == o.c && eps == o.eps && pos == o.pos &&
            vel == o.vel && mass == o.mass && dt == o.dt && precision == o.precision &&
-           splits == o.splits && base == o.base;
+           ipt == o.ipt && splits == o.splits && base == o.base;
   }
 };
 
@@ -806,9 +806,18 @@ int replay_step(DevState& d, const GraphKey& key, int64_t nsteps, hipStream_t st
 }
 
 // ------------------------------------------------------------------ batched ensembles
+// Batched sweep shape per precision (pn_set_batch_shape, from the
+// autotuner's table): i-bodies per lane of every system, and the common
+// j-split count (0: the rule in plan_batch).
+struct BatchShape {
+  int ipt = 1, nsplit = 0;
+};
+BatchShape g_batch_shape[2];
+
 struct BatchPlan {
   std::vector<SysDev> sys;
   std::vector<int> order, pre_pro, pre_pair, pre_epi;
+  int ipt = 1;     // i-bodies per lane (1 or 2), every system
   int splits = 1;  // common j-split count (before the per-system cap)
   size_t o_sys, o_order, o_pre_pro, o_pre_pair, o_pre_epi, o_pk, o_ub, o_bpart, o_part, o_bhpart,
       o_status, o_xs, o_vs, o_kx, o_kv, total;
@@ -816,21 +825,31 @@ struct BatchPlan {
 };
 
 // Shapes, partial-sum slots and launch prefixes of an ensemble.  Every
-// system uses the sweep shape (1 i per lane, 4 wavefronts per i-range); the
-// number of j-splits is common, chosen so the whole ensemble has ~16k sweep
-// workgroups, and capped so each wavefront keeps at least 32 j.
-BatchPlan plan_batch(int n_sys, const int64_t* off, const double* G, const double* c,
-                     const double* eps) {
+// system uses one sweep shape: IPT i-bodies per lane (the installed batched
+// shape of the precision, default 1), 4 wavefronts per i-range; the number of
+// j-splits is common, by default chosen so the whole ensemble has ~16k sweep
+// workgroups, and capped per system so each wavefront keeps at least 32 j.
+// PN_BATCH_SHAPE="ipt,nsplit" overrides the shape (tuning runs).
+// (G, c, eps may be null when only the shape is wanted)
+BatchPlan plan_batch(int n_sys, const int64_t* off, int precision, const double* G = nullptr,
+                     const double* c = nullptr, const double* eps = nullptr) {
   BatchPlan P;
   P.sys.resize(n_sys);
+  BatchShape bs = g_batch_shape[precision == PN_MIXED ? 1 : 0];
+  if (const char* env = getenv("PN_BATCH_SHAPE")) {
+    int a = 0, b = -1;
+    if (sscanf(env, "%d,%d", &a, &b) == 2 && (a == 1 || a == 2) && b >= 0 && b <= 64) {
+      bs.ipt = a;
+      bs.nsplit = b;
+    }
+  }
+  P.ipt = bs.ipt;
+  const int ib = 64 * P.ipt;  // i-bodies per sweep workgroup
   int64_t tot_iblocks = 0;
-  for (int b = 0; b < n_sys; ++b) tot_iblocks += (off[b + 1] - off[b] - 1 + 63) / 64;
+  for (int b = 0; b < n_sys; ++b) tot_iblocks += (off[b + 1] - off[b] - 1 + ib - 1) / ib;
   int ns_common =
       (int)std::max<int64_t>(1, std::min<int64_t>(16, (16384 + tot_iblocks - 1) / tot_iblocks));
-  if (const char* env = getenv("PN_BATCH_SPLITS")) {  // tuning runs
-    const int v = atoi(env);
-    if (v >= 1 && v <= 64) ns_common = v;
-  }
+  if (bs.nsplit > 0) ns_common = bs.nsplit;
   P.splits = ns_common;
   int64_t star0 = 0, part0 = 0;
   int pro0 = 0, epi0 = 0;
@@ -841,7 +860,7 @@ BatchPlan plan_batch(int n_sys, const int64_t* off, const double* G, const doubl
     S.star0 = star0;
     S.part0 = part0;
     S.Ns = Ns;
-    S.iblocks = (Ns + 63) / 64;
+    S.iblocks = (Ns + ib - 1) / ib;
     int ns = std::max(1, std::min(ns_common, Ns / 128));
     S.jchunk = (Ns + ns - 1) / ns;
     S.nsplit = (Ns + S.jchunk - 1) / S.jchunk;
@@ -849,9 +868,11 @@ BatchPlan plan_batch(int n_sys, const int64_t* off, const double* G, const doubl
     S.nepi = (Ns + kEpiStars - 1) / kEpiStars;
     S.pro0 = pro0;
     S.epi0 = epi0;
-    S.G = G[b];
-    S.lam = lambda_of(c[b]);
-    S.eps2 = eps[b] * eps[b];
+    if (G && c && eps) {
+      S.G = G[b];
+      S.lam = lambda_of(c[b]);
+      S.eps2 = eps[b] * eps[b];
+    }
     star0 += Ns;
     part0 += (int64_t)S.nsplit * kNF * Ns;
     pro0 += S.npro;
@@ -932,10 +953,14 @@ int enqueue_batched_step(const BatchPlan& P, char* base, const double* mass, dou
       hipLaunchKernelGGL(k_prologue_batched<double>, dim3(P.pre_pro[n_sys]), dim3(kBlock), 0, st, b);
     HIPCK(hipGetLastError());
     b.pre = pre_pair;
-    if (precision == PN_MIXED)
-      hipLaunchKernelGGL(k_pair_batched<float>, dim3(P.pre_pair[n_sys]), dim3(kBlock), 0, st, b);
-    else
-      hipLaunchKernelGGL(k_pair_batched<double>, dim3(P.pre_pair[n_sys]), dim3(kBlock), 0, st, b);
+    const dim3 gp(P.pre_pair[n_sys]);
+    if (precision == PN_MIXED) {
+      if (P.ipt == 2) hipLaunchKernelGGL((k_pair_batched<float, 2>), gp, dim3(kBlock), 0, st, b);
+      else hipLaunchKernelGGL((k_pair_batched<float, 1>), gp, dim3(kBlock), 0, st, b);
+    } else {
+      if (P.ipt == 2) hipLaunchKernelGGL((k_pair_batched<double, 2>), gp, dim3(kBlock), 0, st, b);
+      else hipLaunchKernelGGL((k_pair_batched<double, 1>), gp, dim3(kBlock), 0, st, b);
+    }
     HIPCK(hipGetLastError());
     b.pre = pre_epi;
     hipLaunchKernelGGL(k_epilogue_batched, dim3(P.pre_epi[n_sys]), dim3(kBlock), 0, st, b);
@@ -1392,7 +1417,7 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
   if (rc) return rc;
   hipStream_t st = pick_stream(*d, stream);
   if ((rc = order_after_previous(*d, st))) return rc;
-  const BatchPlan P = plan_batch(n_sys, offsets, G, c, eps);
+  const BatchPlan P = plan_batch(n_sys, offsets, precision, G, c, eps);
   if ((rc = ensure_batch_scratch(*d, P.total))) return rc;
   char* base = d->bbase;
   int* status = reinterpret_cast<int*>(base + P.o_status);
@@ -1406,6 +1431,7 @@ int pn_step_batched(int32_t n_sys, const int64_t* offsets, const double* G, cons
   key.mass = mass;
   key.dt = dt;
   key.precision = precision;
+  key.ipt = P.ipt;
   key.splits = P.splits;
   key.base = base;
   const bool graph = !(flags & PN_NOGRAPH);
@@ -1486,6 +1512,32 @@ int pn_query_shape(int precision, int64_t N, int* out4) {
   out4[1] = sh.ws;
   out4[2] = sh.nsplit;
   out4[3] = sh.iblocks;
+  return PN_OK;
+}
+
+int pn_set_batch_shape(int precision, int ipt, int nsplit) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (precision < 0) {
+    g_batch_shape[0] = g_batch_shape[1] = BatchShape();
+    return PN_OK;
+  }
+  if ((precision != PN_FP64 && precision != PN_MIXED) || (ipt != 1 && ipt != 2) || nsplit < 0 ||
+      nsplit > 64)
+    return PN_EINVAL;
+  g_batch_shape[precision] = BatchShape{ipt, nsplit};
+  return PN_OK;
+}
+
+int pn_query_batch_shape(int precision, int32_t n_sys, const int64_t* offsets, int* out) {
+  if (n_sys < 1 || !offsets || !out || offsets[0] != 0) return PN_EINVAL;
+  if (precision != PN_FP64 && precision != PN_MIXED) return PN_EINVAL;
+  for (int b = 0; b < n_sys; ++b)
+    if (offsets[b + 1] - offsets[b] < 2) return PN_EINVAL;
+  if (offsets[n_sys] > ((int64_t)1 << 28)) return PN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const BatchPlan P = plan_batch(n_sys, offsets, precision);
+  out[0] = P.ipt;
+  for (int b = 0; b < n_sys; ++b) out[1 + b] = P.sys[b].nsplit;
   return PN_OK;
 }
 

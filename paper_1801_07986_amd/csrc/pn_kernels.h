@@ -1758,7 +1758,8 @@ __global__ __launch_bounds__(kBlock) void k_prologue_batched(BatchArgs b) {
   prologue_block<T>(batch_pro_args<T>(b, S), blockIdx.x - b.pre[r], lds);
 }
 
-template <typename T>
+// IPT i-bodies per lane for every system of the ensemble (the plan's shape)
+template <typename T, int IPT>
 __global__ __launch_bounds__(kBlock) void k_pair_batched(BatchArgs b) {
   using Pk = typename PkOf<T>::type;
   const int r = batch_rank(b.pre, b.n_sys, blockIdx.x);
@@ -1770,8 +1771,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched(BatchArgs b) {
   a.jchunk = S.jchunk;
   a.eps2 = S.eps2;
   a.part = b.part + S.part0;
-  __shared__ double red[pair_red_doubles<T, 1, 4>()];
-  pair_block<T, MODE_FUSED, 1, 4>(a, local % S.iblocks, local / S.iblocks, red);
+  __shared__ double red[pair_red_doubles<T, IPT, 4>()];
+  pair_block<T, MODE_FUSED, IPT, 4>(a, local % S.iblocks, local / S.iblocks, red);
 }
 
 __global__ __launch_bounds__(kBlock) void k_epilogue_batched(BatchArgs b) {

@@ -133,6 +133,38 @@ def test_batched_validation_without_device(lib):
                                None, 0) == EINVAL
 
 
+def test_batch_shape_without_device(lib):
+    """pn_set_batch_shape / pn_query_batch_shape are host-only: the default
+    rule (1 i per lane; a common split count giving ~16k sweep workgroups, at
+    most 16, capped per system at Ns / 128), a forced shape, and argument
+    checks."""
+    from paper_1801_07986_amd import _binding
+
+    EINVAL = -1
+    off = [0, 1000, 1003, 6003]  # Ns = 999, 2, 4999
+    try:
+        for prec in (0, 1):
+            lib.pn_set_batch_shape(prec, 1, 0)
+            ipt, splits = _binding.pn_query_batch_shape(prec, off)
+            tot = -(-999 // 64) + 1 + -(-4999 // 64)
+            common = max(1, min(16, -(-16384 // tot)))
+            assert ipt == 1 and splits == [max(1, min(common, n // 128)) for n in (999, 2, 4999)]
+            lib.pn_set_batch_shape(prec, 2, 5)
+            ipt, splits = _binding.pn_query_batch_shape(prec, off)
+            assert ipt == 2 and splits == [5, 1, 5]
+        assert lib.pn_set_batch_shape(0, 3, 0) == EINVAL
+        assert lib.pn_set_batch_shape(0, 1, 65) == EINVAL
+        assert lib.pn_set_batch_shape(4, 1, 0) == EINVAL
+        out = (ctypes.c_int * 4)()
+        bad = (ctypes.c_int64 * 3)(0, 10, 11)
+        assert lib.pn_query_batch_shape(0, 2, ctypes.cast(bad, ctypes.c_void_p),
+                                        ctypes.cast(out, ctypes.c_void_p)) == EINVAL
+        assert lib.pn_query_batch_shape(0, 0, ctypes.cast(bad, ctypes.c_void_p),
+                                        ctypes.cast(out, ctypes.c_void_p)) == EINVAL
+    finally:
+        _binding.install_tuned_shapes()
+
+
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, 99):
         assert isinstance(lib.pn_strerror(code), bytes)

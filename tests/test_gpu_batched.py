@@ -91,27 +91,44 @@ def test_batched_graph_equals_direct_and_is_deterministic(pn):
         assert np.array_equal(x, y) and np.array_equal(x, z)
 
 
-def test_batched_single_system_matches_pn_step_shape(pn):
-    """One system of N = 5000 in a batch of one, against pn_step with the
-    same shape (1 i per lane, 4 wavefronts, same split count): bitwise."""
-    N = 5000
-    pos, vel, mass = inputs.plummer_bh(N, 0.1, 77)
-    off = [0, N]
-    bp, bv = run_batched(pn, pos, vel, mass, off, [(N, 0.1, 30.0, 1e-4, 0)], 1e-4, 2, 0)
-    Ns = N - 1
-    iblocks = (Ns + 63) // 64
-    ns = max(1, min(min(16, -(-16384 // iblocks)), Ns // 128))  # the batched plan's rule
+def step_alone_in_shape(pn, pos, vel, mass, c, eps, dt, steps, prec, ipt, ns):
+    """pn_step of one system with the sweep shape forced to (ipt, 4 waves, ns)."""
     from paper_1801_07986_amd import _binding
 
+    N = len(mass)
     pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
-    pn.pn_set_shape(0, N, N, 1, 4, ns)
+    pn.pn_set_shape(prec, N, N, ipt, 4, ns)
     try:
         P, V = dev(pos), dev(vel)
-        pn.pn_step(P, V, dev(mass), G, 30.0, 1e-4, 1e-4, 2, 0)
+        pn.pn_step(P, V, dev(mass), G, c, eps, dt, steps, prec)
     finally:
         pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
         _binding.install_tuned_shapes()
-    assert np.array_equal(bp, P.cpu().numpy()) and np.array_equal(bv, V.cpu().numpy())
+    return P.cpu().numpy(), V.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("bshape", [(1, 0), (2, 0), (1, 3), (2, 5)],
+                         ids=["ipt1_rule", "ipt2_rule", "ipt1_ns3", "ipt2_ns5"])
+def test_batched_single_system_matches_pn_step_shape(pn, prec, bshape):
+    """One system of N = 5000 in a batch of one, in each batched sweep shape
+    (1 or 2 i per lane; the split rule or a forced count), against pn_step
+    with the same shape (same i per lane, 4 wavefronts, same split count):
+    bitwise."""
+    from paper_1801_07986_amd import _binding
+
+    N = 5000
+    pos, vel, mass = inputs.plummer_bh(N, 0.1, 77)
+    off = [0, N]
+    pn.pn_set_batch_shape(prec, *bshape)
+    try:
+        ipt, splits = pn.pn_query_batch_shape(prec, off)
+        assert ipt == bshape[0] and (bshape[1] == 0 or splits[0] == bshape[1])
+        bp, bv = run_batched(pn, pos, vel, mass, off, [(N, 0.1, 30.0, 1e-4, 0)], 1e-4, 2, prec)
+    finally:
+        _binding.install_tuned_shapes()
+    sp, sv = step_alone_in_shape(pn, pos, vel, mass, 30.0, 1e-4, 1e-4, 2, prec, ipt, splits[0])
+    assert np.array_equal(bp, sp) and np.array_equal(bv, sv)
 
 
 def test_batched_invalid_mass(pn):
@@ -161,32 +178,22 @@ def ensemble256():
     return systems, np.concatenate(ps), np.concatenate(vs), np.concatenate(ms), off
 
 
-def batch_splits(Ns_all):
-    """The batched plan's j-split count of each system: a common count giving
-    the ensemble ~16k sweep workgroups (at most 16), capped so that every
-    wavefront keeps at least 32 j."""
-    tot = sum(-(-n // 64) for n in Ns_all)
-    common = max(1, min(16, -(-16384 // tot)))
-    return [max(1, min(common, n // 128)) for n in Ns_all]
-
-
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
 def test_ensemble256_members_equal_pn_step(pn, ensemble256, prec):
-    """One batched RK4 step of the whole 256-system ensemble; eight members
-    (the largest, the second largest, the median, the two smallest, and three
-    seeded random ones; the largest and the smallest are the first and the
-    last in the plan's order of decreasing N) bitwise against pn_step of the
-    member alone in the batched plan's shape (1 i per lane, 4 wavefronts, the
-    plan's split count); the two smallest against the oracle's RK4 step too."""
-    from paper_1801_07986_amd import _binding
-
+    """One batched RK4 step of the whole 256-system ensemble in its tuned shape;
+    eight members (the largest, the second largest, the median, the two
+    smallest, and three seeded random ones; the largest and the smallest are
+    the first and the last in the plan's order of decreasing N) bitwise
+    against pn_step of the member alone in the batched plan's shape (its i per
+    lane, 4 wavefronts, the member's split count); the two smallest against
+    the oracle's RK4 step too."""
     systems, pos, vel, mass, off = ensemble256
     Ns = np.array([s["N"] for s in systems])
-    splits = batch_splits([n - 1 for n in Ns])
+    ipt, splits = pn.pn_query_batch_shape(prec, off)
     cs = [s["c"] for s in systems]
     print(f"[case] ensemble of {len(systems)}, {off[-1]} bodies, precision {prec}, "
-          f"split counts {sorted(set(splits))}", flush=True)
+          f"{ipt} i per lane, split counts {sorted(set(splits))}", flush=True)
     bp, bv = run_batched(pn, pos, vel, mass, off, [(s["N"], s["M_bh"], s["c"], s["eps"], 0)
                                                    for s in systems], 1e-4, 1, prec)
     order = np.argsort(-Ns, kind="stable")  # the plan's order: decreasing N
@@ -199,15 +206,9 @@ def test_ensemble256_members_equal_pn_step(pn, ensemble256, prec):
         N, c = int(Ns[k]), cs[k]
         sl = slice(off[k], off[k + 1])
         print(f"[system] {k} N={N} c={c:.1f} splits={splits[k]}", flush=True)
-        pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
-        pn.pn_set_shape(prec, N, N, 1, 4, splits[k])
-        try:
-            P, V = dev(pos[sl]), dev(vel[sl])
-            pn.pn_step(P, V, dev(mass[sl]), G, c, 1e-4, 1e-4, 1, prec)
-        finally:
-            pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
-            _binding.install_tuned_shapes()
-        assert np.array_equal(bp[sl], P.cpu().numpy()) and np.array_equal(bv[sl], V.cpu().numpy())
+        sp, sv = step_alone_in_shape(pn, pos[sl], vel[sl], mass[sl], c, 1e-4, 1e-4, 1, prec, ipt,
+                                     splits[k])
+        assert np.array_equal(bp[sl], sp) and np.array_equal(bv[sl], sv)
         if k in (order[-1], order[-2]):
             rp, rv = oracle.step(pos[sl], vel[sl], mass[sl], G, c, 1e-4, 1e-4, 1)
             dp = np.abs(bp[sl] - rp).max() / np.abs(rp).max()
