@@ -53,8 +53,8 @@ PEAK_FP32_VALU = 157.3e12
 TRAFFIC_BYTES = {
     # FETCH 6306.41 KiB, WRITE 46109.37 KiB per launch
     ("plummer_n16384_fp64", "k_pair_bh<double,3,2,4>", 32): 60131523,
-    # FETCH 64265.38 KiB, WRITE 141502.06 KiB per launch
-    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 24): 276513600,
+    # FETCH 79886.5 KiB, WRITE 188669 KiB per launch
+    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 32): 356804608,
 }
 
 

@@ -223,3 +223,24 @@ def test_bench_refuses_more_than_one_gpu():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stderr
+
+
+def test_table32_oracle_leg_runs_the_protocol():
+    """bench.py's Table 3.2 oracle leg (CPU only): within its time budget it
+    runs energy, 32 RK4 steps, energy; without budget it extrapolates from
+    one evaluation and says so."""
+    import sys
+
+    import numpy as np
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle
+    from paper_1801_07986_amd import inputs
+
+    pos, vel, mass = inputs.cold_sphere_bh(63, seed=3)
+    r = bench.oracle_table32(oracle, pos, vel, mass, samples=3, budget_s=60.0)
+    assert r["runs"] == 3 and r["kind"].startswith("measured") and r["mean_s"] > 0
+    assert np.isfinite(r["std_s"])
+    r = bench.oracle_table32(oracle, pos, vel, mass, samples=3, budget_s=0.0)
+    assert r["runs"] == 0 and r["kind"].startswith("extrapolated") and r["std_s"] is None
