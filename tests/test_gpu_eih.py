@@ -2,7 +2,7 @@
 
 Tolerances as for the limited path (per-body relative error with the
 cancellation floor of test_gpu_parity): FP64 total <= 1e-12, 1PN part <= 1e-11;
-mixed total <= 1e-6, 1PN part <= 1e-5.  N = 2 with equal masses is checked
+mixed total <= 1e-6 (floor s / 2), 1PN part <= 1e-5.  N = 2 with equal masses is checked
 against the textbook two-body 1PN relative acceleration.
 """
 import numpy as np
@@ -51,7 +51,9 @@ def test_eih_parity(pn, N, prec):
     rN, rphi, r1 = oracle.eih2(pos, vel, mass, G, c, eps)
     s = newton_scale(pos, mass, eps)
     tol, tol1 = (1e-12, 1e-11) if prec == 0 else (1e-6, 1e-5)
-    e, e1 = body_rel(aN + a1, rN + r1, s), body_rel(a1, r1, s, 1e-6)
+    # mixed: floor s / 2 (the FP32 pair-term rounding bound, see test_gpu_parity)
+    e = body_rel(aN + a1, rN + r1, s, 1e-3 if prec == 0 else 0.5)
+    e1 = body_rel(a1, r1, s, 1e-6)
     ep = (np.abs(phi - rphi) / np.abs(rphi)).max()
     print(f"N={N} prec={prec}: total {e.max():.3e} 1PN {e1.max():.3e} phi {ep:.3e}")
     assert e.max() <= tol and e1.max() <= tol1
