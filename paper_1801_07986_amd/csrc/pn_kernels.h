@@ -817,11 +817,11 @@ __device__ __forceinline__ void bh_quantities(const EpiArgs& a, double* lds,
   constexpr int K = bh_cols<S>();
   double r[K];
   rows_sum<K>(rows, lds, r);
-  const double M = a.mass[0];
-  A0[0] = get<S>(r, 0, 8) / M;
-  A0[1] = get<S>(r, 1, 8) / M;
-  A0[2] = get<S>(r, 2, 8) / M;
-  V0 = get<S>(r, 3, 8) / M;
+  const double iM = 1.0 / a.mass[0];  // one division for the four quotients
+  A0[0] = get<S>(r, 0, 8) * iM;
+  A0[1] = get<S>(r, 1, 8) * iM;
+  A0[2] = get<S>(r, 2, 8) * iM;
+  V0 = get<S>(r, 3, 8) * iM;
   P[0] = get<S>(r, 4, 8);
   P[1] = get<S>(r, 5, 8);
   P[2] = get<S>(r, 6, 8);
@@ -961,7 +961,8 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   S A0[3], V0, P[3];
   bh_quantities<S>(a, lds, rows, A0, V0, P);  // (its first barrier also orders fsum)
   const double gM = a.G * M;
-  const S w[3] = {-P[0] / M, -P[1] / M, -P[2] / M};
+  const double iM = 1.0 / M;
+  const S w[3] = {-(P[0] * iM), -(P[1] * iM), -(P[2] * iM)};
 
   constexpr bool CHAIN = !std::is_void<PkT>::value;
   constexpr bool JNEXT = std::is_same<PkT, Dual>::value;  // the jerk sweep's packets
