@@ -247,6 +247,30 @@ int pn_set_batch_shape(int precision, int ipt, int nsplit);
 int pn_query_batch_shape(int precision, int32_t n_sys, const int64_t* offsets, int* out);
 
 /*
+ * One launch per Runge-Kutta stage for small systems (the integrator of
+ * Sec. 3.2 / Sec. 4 as pn_step runs it, Eqs. (1)-(6) per stage): pn_step in
+ * the given precision advances systems of n_min <= N <= n_max bodies with one
+ * kernel per stage.  In that kernel each workgroup sums all j for ns stars
+ * (ns = 2, 4, 8 or 16) and runs their epilogue; every workgroup recomputes
+ * the massive object's pending update.  Sizes no entry covers keep the
+ * chained two-kernel stages.  Entries are searched in the order given;
+ * precision < 0 clears them.  Searched by the autotuner.  The choice changes
+ * speed only: both forms meet the same accuracy, each is deterministic, and
+ * a run split over several calls equals one call in either.  The two forms
+ * sum in different orders, so they differ from each other by rounding.  Host
+ * only; PN_EINVAL for a bad precision, n_min < 2, n_max < n_min or ns outside
+ * {2, 4, 8, 16}.
+ */
+int pn_set_stage_kernel(int precision, int64_t n_min, int64_t n_max, int ns);
+
+/*
+ * Stars per workgroup of the one-launch stage that pn_step would use for an
+ * N-body system in the given precision, 0 for the chained two-kernel stages;
+ * PN_EINVAL for a bad precision or N.  Host only.
+ */
+int pn_query_stage_kernel(int precision, int64_t N);
+
+/*
  * Launch shape of the star-star sweep for systems with n_min <= N <= n_max in
  * the given precision (searched by the autotuner; later entries never override
  * earlier ones that match).  ipt: i-bodies per lane (1 or 2); ws: wavefronts

@@ -17,7 +17,7 @@ _BINDING_NAMES = (
     "PN_OK", "PN_EINVAL", "PN_ENONFINITE", "PN_EDEVICE", "PN_ENOMEM", "PN_FP64", "PN_MIXED",
     "PN_ASYNC", "PN_NOGRAPH", "PN_TIMING", "load", "LIB_PATH", "EXPORTS", "pn_set_shape",
     "install_tuned_shapes", "pn_jerk", "pn_step_hermite", "pn_query_shape", "pn_accel_noalloc",
-    "pn_set_batch_shape", "pn_query_batch_shape",
+    "pn_set_batch_shape", "pn_query_batch_shape", "pn_set_stage_kernel", "pn_query_stage_kernel",
 )
 
 

@@ -21,7 +21,7 @@ PN_ASYNC, PN_NOGRAPH, PN_TIMING = 1, 2, 4
 EXPORTS = ("pn_potential_accel", "pn_correction", "pn_accel", "pn_step", "pn_diagnostics",
            "pn_step_batched", "pn_strerror", "pn_last_timing", "pn_release", "pn_set_shape",
            "pn_accel_eih", "pn_encounters", "pn_jerk", "pn_step_hermite", "pn_query_shape", "pn_accel_noalloc", "pn_set_batch_shape",
-           "pn_query_batch_shape")
+           "pn_query_batch_shape", "pn_set_stage_kernel", "pn_query_stage_kernel")
 TUNED_PATH = os.path.join(HERE, "tuned_shapes.json")
 
 
@@ -63,6 +63,8 @@ def load():
         lib.pn_query_shape.argtypes = [i32, i64, vp]
         lib.pn_set_batch_shape.argtypes = [i32, i32, i32]
         lib.pn_query_batch_shape.argtypes = [i32, ctypes.c_int32, vp, vp]
+        lib.pn_set_stage_kernel.argtypes = [i32, i64, i64, i32]
+        lib.pn_query_stage_kernel.argtypes = [i32, i64]
         for name in EXPORTS:
             if name != "pn_strerror":
                 getattr(lib, name).restype = i32
@@ -82,6 +84,7 @@ def install_tuned_shapes(path: str | None = None) -> int:
         table = json.load(f)
     _lib.pn_set_shape(-1, 0, 0, 0, 0, 0)
     _lib.pn_set_batch_shape(-1, 0, 0)
+    _lib.pn_set_stage_kernel(-1, 0, 0, 0)
     n = 0
     for e in table.get("entries", []):
         prec = PN_MIXED if e["precision"] == "mixed" else PN_FP64
@@ -92,6 +95,11 @@ def install_tuned_shapes(path: str | None = None) -> int:
         prec = PN_MIXED if e["precision"] == "mixed" else PN_FP64
         _check(_lib.pn_set_batch_shape(prec, int(e["ipt"]), int(e["nsplit"])),
                "pn_set_batch_shape")
+        n += 1
+    for e in table.get("stage", []):
+        prec = PN_MIXED if e["precision"] == "mixed" else PN_FP64
+        _check(_lib.pn_set_stage_kernel(prec, int(e["n_min"]), int(e["n_max"]), int(e["ns"])),
+               "pn_set_stage_kernel")
         n += 1
     return n
 
@@ -106,6 +114,19 @@ def pn_query_shape(precision, N):
     _check(load().pn_query_shape(precision, int(N), ctypes.cast(out, ctypes.c_void_p)),
            "pn_query_shape")
     return tuple(out)
+
+
+def pn_set_stage_kernel(precision, n_min, n_max, ns):
+    return _check(load().pn_set_stage_kernel(precision, int(n_min), int(n_max), int(ns)),
+                  "pn_set_stage_kernel")
+
+
+def pn_query_stage_kernel(precision, N):
+    """Stars per workgroup of pn_step's one-launch stages for an N-body system (0: two kernels)."""
+    rc = load().pn_query_stage_kernel(precision, int(N))
+    if rc < 0:
+        _check(rc, "pn_query_stage_kernel")
+    return rc
 
 
 def pn_set_batch_shape(precision, ipt, nsplit):

@@ -25,7 +25,13 @@ ensemble (N ~ U{1024..16384}): whole ensemble steps over i-bodies per lane
 precision, and stores the fastest under "batched" in the same table
 (installed with pn_set_batch_shape).
 
-Usage (on the GPU):  python -m paper_1801_07986_amd.autotune [--out PATH] [--quick | --batched]
+With --stage it tunes pn_step's one-launch stages (k_stage) for small
+systems: at each size up to 4096 bodies, whole RK4 steps with 2, 4, 8 or 16
+stars per workgroup against the chained two-kernel stages in their tuned
+shape; the sizes where a one-launch stage wins become "stage" entries of the
+same table (installed with pn_set_stage_kernel).
+
+Usage (on the GPU):  python -m paper_1801_07986_amd.autotune [--out PATH] [--quick | --batched | --stage]
 """
 from __future__ import annotations
 
@@ -80,7 +86,8 @@ def tune(sizes, log=print):
     from paper_1801_07986_amd import inputs
 
     pn.load()
-    pn.pn_set_shape(-1, 0, 0, 0, 0, 0)  # measure without any installed table
+    pn.pn_set_shape(-1, 0, 0, 0, 0, 0)  # measure without any installed table,
+    pn.pn_set_stage_kernel(-1, 0, 0, 0)  # with the chained stages
     results = []
     for N in sizes:
         pos, vel, mass = inputs.plummer_bh(N, 0.1, 9)
@@ -159,6 +166,56 @@ def tune_batched(log=print, steps=2, reps=2):
     return out
 
 
+STAGE_SIZES = [100, 300, 1024, 2048, 4096]
+STAGE_NS = (2, 4, 8, 16)
+
+
+def tune_stage(log=print):
+    """Sizes (and stars per workgroup) where pn_step's one-launch stages beat
+    the chained stages in the installed shapes; whole RK4 steps."""
+    import torch
+
+    import paper_1801_07986_amd as pn
+    from paper_1801_07986_amd import inputs
+
+    pn.load()  # the chained stages keep the installed shape table
+    pn.pn_set_stage_kernel(-1, 0, 0, 0)
+    rows = []
+    for N in STAGE_SIZES:
+        pos, vel, mass = inputs.plummer_bh(N, 0.1, 9)
+        P = torch.from_numpy(pos).cuda()
+        V = torch.from_numpy(vel).cuda()
+        Mm = torch.from_numpy(mass).cuda()
+        for prec_name, prec in (("fp64", pn.PN_FP64), ("mixed", pn.PN_MIXED)):
+            os.environ["PN_STAGE_NS"] = "0"
+            chain = time_step(pn, torch, P, V, Mm, prec)
+            best = (chain, 0)
+            for ns in STAGE_NS:
+                os.environ["PN_STAGE_NS"] = str(ns)
+                ms = time_step(pn, torch, P, V, Mm, prec)
+                log(f"[autotune]   N={N} {prec_name} one-launch stages, {ns} stars per workgroup: "
+                    f"{ms:.4f} ms/step")
+                if ms < best[0]:
+                    best = (ms, ns)
+            rows.append(dict(N=N, precision=prec_name, ns=best[1], step_ms=best[0],
+                             chain_step_ms=chain))
+            log(f"[autotune] N={N} {prec_name}: chained {chain:.4f} ms/step, best "
+                f"{'chained' if best[1] == 0 else f'{best[1]} stars per workgroup'} {best[0]:.4f}")
+    os.environ.pop("PN_STAGE_NS", None)
+    entries = []
+    for prec in ("fp64", "mixed"):
+        rs = sorted((r for r in rows if r["precision"] == prec), key=lambda r: r["N"])
+        for k, r in enumerate(rs):
+            if r["ns"] == 0:
+                continue
+            lo = 2 if k == 0 else int(math.sqrt(rs[k - 1]["N"] * r["N"])) + 1
+            hi = int(math.sqrt(r["N"] * (rs[k + 1]["N"] if k + 1 < len(rs) else 2 * r["N"])))
+            entries.append(dict(precision=prec, n_min=lo, n_max=hi, ns=r["ns"], measured_N=r["N"],
+                                step_ms=round(r["step_ms"], 5),
+                                chain_step_ms=round(r["chain_step_ms"], 5)))
+    return entries
+
+
 def to_table(results):
     entries = []
     for prec in ("fp64", "mixed"):
@@ -181,6 +238,8 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--batched", action="store_true",
                     help="tune pn_step_batched's shape only (kept with the existing table)")
+    ap.add_argument("--stage", action="store_true",
+                    help="tune pn_step's one-launch stages only (kept with the existing table)")
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     old = {}
@@ -191,11 +250,16 @@ def main(argv=None):
         table = dict(old)
         table["batched"] = tune_batched(log=log)
         table["batched_created"] = time.strftime("%Y-%m-%d %H:%M:%S")
+    elif args.stage:
+        table = dict(old)
+        table["stage"] = tune_stage(log=log)
+        table["stage_created"] = time.strftime("%Y-%m-%d %H:%M:%S")
     else:
         table = to_table(tune(QUICK_SIZES if args.quick else SIZES, log=log))
-        if "batched" in old:
-            table["batched"] = old["batched"]
-            table["batched_created"] = old.get("batched_created")
+        for key in ("batched", "stage"):
+            if key in old:
+                table[key] = old[key]
+                table[key + "_created"] = old.get(key + "_created")
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
         f.write("\n")

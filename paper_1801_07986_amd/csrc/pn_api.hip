@@ -106,12 +106,34 @@ Shape with_splits(Shape s, int Ns, int want) {
   return s;
 }
 
+// One-launch Runge-Kutta stages (k_stage) for small systems: entries
+// (precision, n_min <= N <= n_max, stars per workgroup) installed with
+// pn_set_stage_kernel (the autotuner's table); no matching entry: the chained
+// two-kernel stages.  PN_STAGE_NS=ns overrides it for every size (tuning
+// runs; 0 turns it off).
+struct StageSel {
+  int precision;
+  int64_t n_min, n_max;
+  int ns;
+};
+std::vector<StageSel> g_stage;
+bool stage_ns_ok(int ns) { return ns == 2 || ns == 4 || ns == 8 || ns == 16; }
+int pick_stage_ns(int64_t N, int precision) {
+  if (const char* env = getenv("PN_STAGE_NS")) {
+    const int v = atoi(env);
+    return stage_ns_ok(v) ? v : 0;
+  }
+  for (const StageSel& t : g_stage)
+    if (t.precision == precision && N >= t.n_min && N <= t.n_max) return t.ns;
+  return 0;
+}
+
 // ------------------------------------------------------------------ scratch
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t pk, ub, bpart, ub2, bpart2, bhpart2, part, bhpart, status, xs, vs, kx, kv, dpart, out8, ha, hj, xp, vp, ap,
-      total;
+      pk2, bpart3, bpart4, bhs, total;
 };
 
 // What a call needs beyond one force evaluation: the RK4 stage arrays, or the
@@ -119,7 +141,10 @@ struct Layout {
 // Hermite state.
 enum class Need { EVAL, RK4, JERK, HERMITE };
 
-Layout layout_for(int64_t N, const Shape& s, Need need) {
+// stage_ns > 0 (RK4 only): the one-launch stages' extra buffers (k_stage:
+// a second packet buffer, four block-row buffers of a row per stage_ns stars,
+// two massive-object row buffers and two copies of its state).
+Layout layout_for(int64_t N, const Shape& s, Need need, int stage_ns = 0) {
   const bool rk4 = need == Need::RK4;
   const bool dual = need == Need::JERK || need == Need::HERMITE;
   const bool herm = need == Need::HERMITE;
@@ -138,15 +163,22 @@ Layout layout_for(int64_t N, const Shape& s, Need need) {
   // evaluations: each stage's epilogue writes the next stage's u/b rows and
   // block rows into the other of two buffers; a jerk evaluation's FP64
   // epilogue writes the jerk sweep's (dual) rows into the second buffers.
-  const size_t nrows = nb * kProRows;
+  const bool fused = rk4 && stage_ns > 0;
+  const size_t nbf = fused ? (Ns + stage_ns - 1) / stage_ns : 0;  // k_stage workgroups = rows
+  const size_t nrows = std::max(nb * kProRows, nbf);
+  const size_t nepi = std::max((Ns + kEpiStars - 1) / kEpiStars, nbf);
   L.pk = take(Ns * (dual ? sizeof(PkDual) : sizeof(PkF64)));
   L.ub = take(Ns * 4 * W * sizeof(double));
   L.bpart = take(nrows * 8 * W * sizeof(double));
   L.ub2 = take(rk4 || dual ? Ns * 4 * W * sizeof(double) : 0);
   L.bpart2 = take(rk4 || dual ? nrows * 8 * W * sizeof(double) : 0);
   L.part = take((size_t)s.nsplit * std::max<size_t>(kNF * W, kND) * Ns * sizeof(double));
-  L.bhpart = take(((Ns + kEpiStars - 1) / kEpiStars) * 4 * W * sizeof(double));
-  L.bhpart2 = take(dual ? ((Ns + kEpiStars - 1) / kEpiStars) * 4 * W * sizeof(double) : 0);
+  L.bhpart = take(nepi * 4 * W * sizeof(double));
+  L.bhpart2 = take(dual || fused ? nepi * 4 * W * sizeof(double) : 0);
+  L.pk2 = take(fused ? Ns * sizeof(PkF64) : 0);
+  L.bpart3 = take(fused ? nbf * 8 * sizeof(double) : 0);
+  L.bpart4 = take(fused ? nbf * 8 * sizeof(double) : 0);
+  L.bhs = take(fused ? 36 * sizeof(double) : 0);
   L.status = take(sizeof(int));
   L.dpart = take(nb * 10 * sizeof(double));
   L.out8 = take(8 * sizeof(double));
@@ -178,13 +210,14 @@ struct GraphKey {
   int64_t N = 0;
   double G = 0, c = 0, eps = 0, dt = 0;
   int precision = -1, ipt = 0, ws = 0, nsplit = 0;
+  int stage_ns = 0;  // one-launch stages (k_stage): stars per workgroup
   int scheme = 0;  // 0: Runge-Kutta step, 1: Hermite step
   char* base = nullptr;
   bool operator==(const GraphKey& o) const {
     return scheme == o.scheme && pos == o.pos && vel == o.vel && mass == o.mass && N == o.N && G == o.G &&
            (c == o.c || (std::isinf(c) && std::isinf(o.c))) && eps == o.eps && dt == o.dt &&
            precision == o.precision && ipt == o.ipt && ws == o.ws && nsplit == o.nsplit &&
-           base == o.base;
+           stage_ns == o.stage_ns && base == o.base;
   }
 };
 
@@ -675,6 +708,123 @@ int enqueue_rk4_body(const Sys& s, const Ptrs& P, const Shape& sh, int precision
     } else if ((rc = launch_bh_final(a, st))) {
       return rc;
     }
+  }
+  return PN_OK;
+}
+
+// One-launch Runge-Kutta stages (k_stage, small systems).  Buffers of stage k:
+// packets and u/b rows k % 2, block rows k % 4, massive-object 1PN rows
+// k % 2, massive-object state read from copy k % 2 and written to the other.
+struct StageBufs {
+  void* pk[2];
+  double* ub[2];
+  double* bpart[4];
+  double* bhpart[2];
+  double* bhs[2];
+  int nb;  // workgroups = rows per row buffer
+};
+StageBufs stage_bufs(const Ptrs& P, int64_t N, int ns) {
+  StageBufs b;
+  b.pk[0] = P.at<void>(P.L.pk);
+  b.pk[1] = P.at<void>(P.L.pk2);
+  b.ub[0] = P.at<double>(P.L.ub);
+  b.ub[1] = P.at<double>(P.L.ub2);
+  b.bpart[0] = P.at<double>(P.L.bpart);
+  b.bpart[1] = P.at<double>(P.L.bpart2);
+  b.bpart[2] = P.at<double>(P.L.bpart3);
+  b.bpart[3] = P.at<double>(P.L.bpart4);
+  b.bhpart[0] = P.at<double>(P.L.bhpart);
+  b.bhpart[1] = P.at<double>(P.L.bhpart2);
+  b.bhs[0] = P.at<double>(P.L.bhs);
+  b.bhs[1] = b.bhs[0] + 18;
+  b.nb = (int)((N - 1 + ns - 1) / ns);
+  return b;
+}
+
+template <typename T, int NS>
+void launch_stage_t(const StageArgs& sa, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_stage<T, NS>), dim3(grid), dim3(kBlock), 0, st, sa);
+}
+template <typename T>
+int launch_stage_ns(const StageArgs& sa, int grid, int ns, hipStream_t st) {
+  switch (ns) {
+    case 2: launch_stage_t<T, 2>(sa, grid, st); break;
+    case 4: launch_stage_t<T, 4>(sa, grid, st); break;
+    case 8: launch_stage_t<T, 8>(sa, grid, st); break;
+    case 16: launch_stage_t<T, 16>(sa, grid, st); break;
+    default: return fail_inval("stars per workgroup of the stage kernel: 2, 4, 8 or 16");
+  }
+  HIPCK(hipGetLastError());
+  return PN_OK;
+}
+
+// Stage `stage` of a step (mode kStageFirst / kStageFull), or the last
+// pending update (kStageFinal, with stage 0: it reads what stage 0 would).
+int launch_stage(const Sys& s, const Ptrs& P, const Shape& sh, int precision, double dt,
+                 double* X, double* V, int stage, int mode, int ns, hipStream_t st) {
+  Sys e;
+  Outs o;
+  rk4_stage(s, P, precision, dt, X, V, stage, e, o);
+  EpiArgs a = epi_args(e, P, sh, o);
+  const StageBufs b = stage_bufs(P, s.N, ns);
+  a.ub = b.ub[stage & 1];
+  a.bpart = b.bpart[stage];
+  a.nbpro = b.nb;
+  a.bhpart = b.bhpart[stage & 1];
+  a.nbepi = b.nb;
+  a.pk_next = b.pk[(stage + 1) & 1];
+  a.ub_next = b.ub[(stage + 1) & 1];
+  a.bpart_next = b.bpart[(stage + 1) & 3];
+  StageArgs sa;
+  sa.e = a;
+  sa.pk = b.pk[stage & 1];
+  sa.mode = mode;
+  sa.pstage = (stage + 3) & 3;
+  sa.prow = b.bpart[(stage + 3) & 3];
+  sa.phrow = b.bhpart[((stage + 3) & 3) & 1];
+  sa.bhs_in = b.bhs[stage & 1];
+  sa.bhs_out = b.bhs[(stage + 1) & 1];
+  const int grid = mode == kStageFinal ? 1 : b.nb;
+  return precision == PN_MIXED ? launch_stage_ns<float>(sa, grid, ns, st)
+                               : launch_stage_ns<double>(sa, grid, ns, st);
+}
+
+// A call's first packets and rows in the stage kernel's layout.
+template <typename T>
+int launch_stage_head_t(const EpiArgs& a, int grid, int ns, hipStream_t st) {
+  switch (ns) {
+    case 2: hipLaunchKernelGGL((k_stage_head<T, 2>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_stage_head<T, 4>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_stage_head<T, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_stage_head<T, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    default: return fail_inval("stars per workgroup of the stage kernel: 2, 4, 8 or 16");
+  }
+  HIPCK(hipGetLastError());
+  return PN_OK;
+}
+int launch_stage_head(const Sys& s, const Ptrs& P, const Shape& sh, int precision, int ns,
+                      hipStream_t st) {
+  Outs o;
+  EpiArgs a = epi_args(s, P, sh, o);
+  const StageBufs b = stage_bufs(P, s.N, ns);
+  a.pk_next = b.pk[0];
+  a.ub_next = b.ub[0];
+  a.bpart_next = b.bpart[0];
+  return precision == PN_MIXED ? launch_stage_head_t<float>(a, b.nb, ns, st)
+                               : launch_stage_head_t<double>(a, b.nb, ns, st);
+}
+
+// The four stages of one step; the first step of a call starts without a
+// pending update.
+int enqueue_stage_step(const Sys& s, const Ptrs& P, const Shape& sh, int precision, double dt,
+                       double* X, double* V, int ns, bool first, hipStream_t st, Timer* tm) {
+  for (int stage = 0; stage < 4; ++stage) {
+    int rc;
+    if (tm && (rc = tm->begin(st))) return rc;
+    rc = launch_stage(s, P, sh, precision, dt, X, V, stage,
+                      first && stage == 0 ? kStageFirst : kStageFull, ns, st);
+    if (rc) return rc;
+    if (tm && (rc = tm->end(st))) return rc;
   }
   return PN_OK;
 }
@@ -1172,7 +1322,8 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
   DevState* d;
   if ((rc = dev_state(&d))) return rc;
   const Shape sh = pick_shape((int)(N - 1), precision);
-  const Layout L = layout_for(N, sh, Need::RK4);
+  const int ns = pick_stage_ns(N, precision);
+  const Layout L = layout_for(N, sh, Need::RK4, ns);
   if ((rc = ensure_scratch(*d, L.total))) return rc;
   Ptrs P{d->base, L};
   hipStream_t st = pick_stream(*d, stream);
@@ -1181,7 +1332,41 @@ int pn_step(double* pos, double* vel, const double* mass, int64_t N, double G, d
   if ((rc = reset_status(P, st))) return rc;
   const bool timing = (flags & PN_TIMING) != 0;
   const bool graph = !(flags & (PN_NOGRAPH | PN_TIMING));
-  if (nsteps > 0) {
+  if (nsteps > 0 && ns > 0) {
+    // one launch per stage: the head, the first step, nsteps - 1 further
+    // steps (replayed from a graph), the last pending update
+    Timer tm;
+    tm.d = d;
+    tm.on = timing;
+    if ((rc = launch_stage_head(s, P, sh, precision, ns, st))) return rc;
+    if ((rc = enqueue_stage_step(s, P, sh, precision, dt, pos, vel, ns, true, st, &tm))) return rc;
+    if (nsteps > 1) {
+      if (!graph) {
+        for (int64_t k = 1; k < nsteps; ++k)
+          if ((rc = enqueue_stage_step(s, P, sh, precision, dt, pos, vel, ns, false, st, &tm)))
+            return rc;
+      } else {
+        GraphKey key;
+        key.pos = pos;
+        key.vel = vel;
+        key.mass = mass;
+        key.N = N;
+        key.G = G;
+        key.c = c;
+        key.eps = eps;
+        key.dt = dt;
+        key.precision = precision;
+        key.stage_ns = ns;
+        key.base = d->base;
+        rc = replay_step(*d, key, nsteps - 1, st, [&](hipStream_t cs) {
+          return enqueue_stage_step(s, P, sh, precision, dt, pos, vel, ns, false, cs, nullptr);
+        });
+        if (rc) return rc;
+      }
+    }
+    if ((rc = launch_stage(s, P, sh, precision, dt, pos, vel, 0, kStageFinal, ns, st))) return rc;
+    if ((rc = tm.collect((double)(N - 1) * (double)(N - 2)))) return rc;
+  } else if (nsteps > 0) {
     if ((rc = launch_prologue(s, P, precision, st))) return rc;  // stage 0's packets, buffer 0
     if (!graph) {
       Timer tm;
@@ -1513,6 +1698,26 @@ int pn_query_shape(int precision, int64_t N, int* out4) {
   out4[2] = sh.nsplit;
   out4[3] = sh.iblocks;
   return PN_OK;
+}
+
+int pn_set_stage_kernel(int precision, int64_t n_min, int64_t n_max, int ns) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (precision < 0) {
+    g_stage.clear();
+    return PN_OK;
+  }
+  if ((precision != PN_FP64 && precision != PN_MIXED) || n_min < 2 || n_max < n_min ||
+      !stage_ns_ok(ns))
+    return PN_EINVAL;
+  g_stage.push_back(StageSel{precision, n_min, n_max, ns});
+  return PN_OK;
+}
+
+int pn_query_stage_kernel(int precision, int64_t N) {
+  if (N < 2 || N > ((int64_t)1 << 28)) return PN_EINVAL;
+  if (precision != PN_FP64 && precision != PN_MIXED) return PN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return pick_stage_ns(N, precision);
 }
 
 int pn_set_batch_shape(int precision, int ipt, int nsplit) {

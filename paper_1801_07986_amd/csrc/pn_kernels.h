@@ -34,6 +34,10 @@
 // k_bh_final work (the sweep reads only star packets), so a step is eight
 // kernels.  Massive-object block rows hold 64 stars in every kernel, summed
 // in the same tree, so whichever kernel writes a row it holds the same sum.
+// For small systems k_stage runs a whole stage in one launch (each workgroup
+// sums all j for a few stars and runs their epilogue; every workgroup
+// recomputes the massive object's pending update), four kernels per step.
+// All reductions of the O(N) kernels are wavefront xor butterflies.
 //
 // The same four kernels instantiated on dual numbers (T = S = Dual) give the
 // time derivative of the force along the motion (the jerk of the Hermite
@@ -234,24 +238,34 @@ __device__ __forceinline__ void block_sum(const double (&v)[K], double* lds) {
   }
 }
 
-// Per-wavefront sums of K doubles per thread (64 values each, tree order);
-// the sum of wavefront w in lds[k*kBlock + 64 w].  The prologue (a row per
-// wavefront) and the epilogue (its stars in wavefront 0) reduce their
+// Sum over the 64 lanes of a wavefront by an xor butterfly (exchange
+// distances 32, 16, ..., 1).  Both lanes of every exchange add the same two
+// values, so every lane ends with the same bits, and no barrier is needed.
+template <int K>
+__device__ __forceinline__ void wave_allsum(double (&v)[K]) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], m, 64);
+  }
+}
+
+// Per-wavefront sums of K doubles per thread (wave_allsum), the sum of
+// wavefront w in lds[k*kBlock + 64 w] after one barrier.  The prologue (a row
+// per wavefront) and the epilogues (their stars in wavefront 0) reduce their
 // massive-object rows this way, so that a row holds the same sum whichever
 // kernel wrote it.
 template <int K>
 __device__ __forceinline__ void wave_sums(const double (&v)[K], double* lds) {
-  const int t = threadIdx.x, l = t & 63;
+  double s[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) lds[k * kBlock + t] = v[k];
-  __syncthreads();
-  for (int s = 32; s > 0; s >>= 1) {
-    if (l < s) {
+  for (int k = 0; k < K; ++k) s[k] = v[k];
+  wave_allsum<K>(s);
+  if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) lds[k * kBlock + t] += lds[k * kBlock + t + s];
-    }
-    __syncthreads();
+    for (int k = 0; k < K; ++k) lds[k * kBlock + threadIdx.x] = s[k];
   }
+  __syncthreads();
 }
 
 // Wave index as a scalar (so that loop bounds derived from it stay uniform
@@ -259,32 +273,32 @@ __device__ __forceinline__ void wave_sums(const double (&v)[K], double* lds) {
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Sum of `rows` partial rows of width `stride` (first K columns), fixed order:
-// thread t sums rows t, t+kBlock, ..., then a tree.  Same result in every block.
+// lane l of every wavefront sums rows l, l+64, ..., then wave_allsum.  Every
+// thread of every workgroup ends with the same bits, without a barrier.
 // Split in two so that a kernel can request the rows of several sums before
-// waiting for any: rows_load (this thread's partial sums), then rows_sum.
+// waiting for any: rows_load (this lane's partial sums), then rows_sum.
 template <int K>
 __device__ __forceinline__ void rows_load(const double* part, int rows, int stride,
                                           double (&v)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = 0.0;
-  for (int r = threadIdx.x; r < rows; r += kBlock) {
+  for (int r = threadIdx.x & 63; r < rows; r += 64) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += part[(size_t)r * stride + k];
   }
 }
 template <int K>
-__device__ __forceinline__ void rows_sum(const double (&v)[K], double* lds, double (&out)[K]) {
-  block_sum<K>(v, lds);
+__device__ __forceinline__ void rows_sum(const double (&v)[K], double (&out)[K]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) out[k] = lds[k * kBlock];
-  __syncthreads();
+  for (int k = 0; k < K; ++k) out[k] = v[k];
+  wave_allsum<K>(out);
 }
 template <int K>
 __device__ __forceinline__ void reduce_rows(const double* part, int rows, int stride,
-                                            double* lds, double (&out)[K]) {
+                                            double (&out)[K]) {
   double v[K];
   rows_load<K>(part, rows, stride, v);
-  rows_sum<K>(v, lds, out);
+  rows_sum<K>(v, out);
 }
 
 __global__ void k_reset_status(int* status) {
@@ -811,12 +825,12 @@ constexpr int bh_cols() { return IsDual<S>::value ? 16 : 7; }  // columns read p
 
 // rows: this thread's partial sums of the prologue rows (rows_load)
 template <typename S>
-__device__ __forceinline__ void bh_quantities(const EpiArgs& a, double* lds,
+__device__ __forceinline__ void bh_quantities(const EpiArgs& a,
                                               const double (&rows)[bh_cols<S>()], S (&A0)[3],
                                               S& V0, S (&P)[3]) {
   constexpr int K = bh_cols<S>();
   double r[K];
-  rows_sum<K>(rows, lds, r);
+  rows_sum<K>(rows, r);
   const double iM = 1.0 / a.mass[0];  // one division for the four quotients
   A0[0] = get<S>(r, 0, 8) * iM;
   A0[1] = get<S>(r, 1, 8) * iM;
@@ -851,23 +865,48 @@ __device__ __forceinline__ bool epi_field_used(int f, const EpiArgs& a) {
 // massive object's next position; Dual, the jerk sweep's at this state, with
 // the derivatives (v, a) of (x, v) from the acceleration just computed.
 // void: none.
-template <typename S, typename PkT = void>
-__device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double* lds,
-                                               double* fsum) {
+// The massive object's state at an evaluation, for an epilogue whose kernel
+// computes it (the one-launch Runge-Kutta stage) instead of reading it.
+struct BhStage {
+  double x0[3];  // evaluation position
+  double X[3];   // step-start position
+  double KX[3];  // stage sum of its velocities through the previous stage
+  double v[3];   // evaluation velocity
+};
+
+// The epilogue of NSTAR stars (blk * NSTAR ...), from the prologue rows `rows`
+// (this thread's rows_load).  OWNBH = false: the stars' pair sums are the
+// nsplit partials in a.part, the massive object's state is read from a.pos,
+// a.X, a.KX, a.vel.  OWNBH = true (S = double only): the caller has put the
+// pair sums in fsum[field][NSTAR] and passes the massive object's state in own.
+template <typename S, typename PkT, int NSTAR, bool OWNBH>
+__device__ __forceinline__ void epilogue_rows(const EpiArgs& a, int blk, double* lds,
+                                              double* fsum, const double (&rows)[bh_cols<S>()],
+                                              const BhStage& own) {
   constexpr bool DUAL = IsDual<S>::value;
   constexpr int W = DUAL ? 2 : 1;
   constexpr int NFO = kNF * W;
+  static_assert(NSTAR <= 64, "the stars of a workgroup are in its first wavefront");
+  static_assert(OWNBH || NSTAR == kEpiStars, "the split reduction takes 4 threads per star");
+  static_assert(!OWNBH || (!DUAL && !std::is_void<PkT>::value), "own state: chained FP64 epilogue");
   // Every global read of the workgroup is requested before the first wait:
-  // the prologue rows, the pair partials, the star's own inputs and Runge-Kutta
-  // state, the massive object's state.  (At small N this kernel is a chain of
-  // memory latencies; issued in order, they added up.)
-  double rows[bh_cols<S>()];
-  rows_load<bh_cols<S>()>(a.bpart, a.nbpro, DUAL ? 16 : 8, rows);
+  // the prologue rows (by the caller), the pair partials, the star's own
+  // inputs and Runge-Kutta state, the massive object's state.  (At small N
+  // this kernel is a chain of memory latencies; issued in order, they added
+  // up.)
   const double M = a.mass[0];
-  const S x0 = ld<S>(a.pos, a.pos_d, 0), y0 = ld<S>(a.pos, a.pos_d, 1),
-          z0 = ld<S>(a.pos, a.pos_d, 2);
-  const int k = blk * kEpiStars + threadIdx.x;
-  const bool star = threadIdx.x < kEpiStars && k < a.Ns;
+  S x0, y0, z0;
+  if constexpr (OWNBH) {
+    x0 = own.x0[0];
+    y0 = own.x0[1];
+    z0 = own.x0[2];
+  } else {
+    x0 = ld<S>(a.pos, a.pos_d, 0);
+    y0 = ld<S>(a.pos, a.pos_d, 1);
+    z0 = ld<S>(a.pos, a.pos_d, 2);
+  }
+  const int k = blk * NSTAR + threadIdx.x;
+  const bool star = threadIdx.x < NSTAR && k < a.Ns;
   const int i = k + 1;
   S ui = 0.0, bx = 0.0, by = 0.0, bz = 0.0, xi = 0.0, yi = 0.0, zi = 0.0;
   S vi[3] = {0.0, 0.0, 0.0};
@@ -876,7 +915,13 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   // the massive object's step-start position, stage sum and velocity (uniform:
   // scalar loads)
   double bh_x[3] = {0.0, 0.0, 0.0}, bh_kx[3] = {0.0, 0.0, 0.0}, bh_v[3] = {0.0, 0.0, 0.0};
-  if constexpr (!DUAL && !std::is_void<PkT>::value) {
+  if constexpr (OWNBH) {
+    for (int c = 0; c < 3; ++c) {
+      bh_x[c] = own.X[c];
+      bh_kx[c] = a.stage == 0 ? 0.0 : own.KX[c];
+      bh_v[c] = own.v[c];
+    }
+  } else if constexpr (!DUAL && !std::is_void<PkT>::value) {
     if (a.stage >= 0) {
       for (int c = 0; c < 3; ++c) {
         bh_x[c] = a.X[c];
@@ -908,7 +953,7 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   // split reduction: thread (g, l) sums fields g, g+4, g+8, ... of star l, in
   // split order; the loads of up to 8 (dual: 4) splits of all its fields are
   // issued together, then added in order
-  {
+  if constexpr (!OWNBH) {
     constexpr int FPT = (NFO + 3) / 4;      // fields per thread
     constexpr int BATCH = DUAL ? 4 : 8;     // splits per batch of loads
     const int g = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -958,8 +1003,9 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
         if (g + 4 * fi < NFO) fsum[(g + 4 * fi) * kEpiStars + l] = sum[fi];
     }
   }
+  if constexpr (!OWNBH) __syncthreads();  // fsum complete (the caller orders its own)
   S A0[3], V0, P[3];
-  bh_quantities<S>(a, lds, rows, A0, V0, P);  // (its first barrier also orders fsum)
+  bh_quantities<S>(a, rows, A0, V0, P);
   const double gM = a.G * M;
   const double iM = 1.0 / M;
   const S w[3] = {-(P[0] * iM), -(P[1] * iM), -(P[2] * iM)};
@@ -977,8 +1023,8 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
     S sum[kNF];
 #pragma unroll
     for (int f = 0; f < kNF; ++f) {
-      if constexpr (DUAL) sum[f] = S(fsum[f * kEpiStars + t], fsum[(kNF + f) * kEpiStars + t]);
-      else sum[f] = fsum[f * kEpiStars + t];
+      if constexpr (DUAL) sum[f] = S(fsum[f * NSTAR + t], fsum[(kNF + f) * NSTAR + t]);
+      else sum[f] = fsum[f * NSTAR + t];
     }
     sum[F_C2] *= kSqrt32;  // the sweep accumulates D'/sqrt(3/2)
     // Newtonian part: g_i - b_i with g_i = -G_i
@@ -1109,6 +1155,14 @@ __device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double
   }
 }
 
+template <typename S, typename PkT = void>
+__device__ __forceinline__ void epilogue_block(const EpiArgs& a, int blk, double* lds,
+                                               double* fsum) {
+  double rows[bh_cols<S>()];
+  rows_load<bh_cols<S>()>(a.bpart, a.nbpro, IsDual<S>::value ? 16 : 8, rows);
+  epilogue_rows<S, PkT, kEpiStars, false>(a, blk, lds, fsum, rows, BhStage{});
+}
+
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_epilogue(EpiArgs a) {
   __shared__ double lds[(IsDual<S>::value ? 16 : 7) * kBlock];
@@ -1143,11 +1197,11 @@ __device__ __forceinline__ void bh_final_block(const EpiArgs& a, double* lds) {
     if constexpr (!DUAL) rkc = rk4_load(a, (size_t)cc);
   }
   S A0[3], V0, P[3];
-  bh_quantities<S>(a, lds, rows, A0, V0, P);
+  bh_quantities<S>(a, rows, A0, V0, P);
   S T[3] = {0.0, 0.0, 0.0};
   if (!a.newton_only) {
     double r[4 * W - 1];
-    rows_sum<4 * W - 1>(rows1, lds, r);
+    rows_sum<4 * W - 1>(rows1, r);
     for (int c = 0; c < 3; ++c) T[c] = get<S>(r, c, 4);
   }
   // component c of the massive object's outputs and update (c a constant in
@@ -1211,6 +1265,229 @@ __global__ __launch_bounds__(kBlock) void k_pair_bh(PairArgs a, EpiArgs e) {
     return;
   }
   pair_block<T, MODE, IPT, WS>(a, blockIdx.x, blockIdx.y, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Small systems: one launch per Runge-Kutta stage.  Each kernel boundary of a
+// chained step costs several microseconds however little work the kernels
+// do, so below a few thousand bodies a stage is one kernel: a workgroup owns
+// NS stars and sums all their j in its own 256 lanes (lane sl + NS q takes
+// star sl and j = q, q + 256/NS, ...), reduces them in LDS in fixed order and
+// runs those stars' epilogue.  No other workgroup's partials are needed, so
+// nothing waits across workgroups.  The massive object's update of the
+// previous stage needs every epilogue's rows; each workgroup computes it
+// itself from the rows the previous launch wrote (the same sums in the same
+// order, so the same bits everywhere), and workgroup 0 stores it.  Every
+// buffer a stage reads is one no workgroup of that stage writes: packets, u/b
+// rows and massive-object 1PN rows alternate between two buffers, block rows
+// rotate through four (a stage reads its own and the previous stage's), and
+// the massive object's state alternates between two copies of
+// (X, V, Xs, Vs, KX, KV).
+// ---------------------------------------------------------------------------
+constexpr int kStageFirst = 0;  // the first stage of a call: no pending update
+constexpr int kStageFull = 1;   // pending update, sweep and epilogue
+constexpr int kStageFinal = 2;  // the last pending update only (one workgroup)
+
+struct StageArgs {
+  EpiArgs e;             // this stage's epilogue; e.nbpro rows in every row buffer
+  const void* pk;        // this stage's packets (PkOf<T>)
+  int mode;
+  int pstage;            // stage of the pending massive-object update
+  const double* prow;    // its block rows [e.nbpro][8]
+  const double* phrow;   // its massive-object 1PN rows [e.nbpro][4]
+  const double* bhs_in;  // the massive object's X, V, Xs, Vs, KX, KV before that update
+  double* bhs_out;       // ... after it
+};
+
+// The stars' pair sums of one workgroup (lanes of star sl: sl + NS q).
+template <typename T, int NS>
+__device__ __forceinline__ void stage_sweep(const StageArgs& sa, double (&acc)[kNF][1]) {
+  using Pk = typename PkOf<T>::type;
+  constexpr int Q = kBlock / NS;
+  const Pk* __restrict__ pk = static_cast<const Pk*>(sa.pk);
+  const int Ns = sa.e.Ns;
+  const int sl = threadIdx.x % NS, q = threadIdx.x / NS;
+  PairI<T, 1> I;
+  I.idx[0] = blockIdx.x * NS + sl;
+  {
+    const Pk& p = pk[min(I.idx[0], Ns - 1)];  // lanes past the end compute on a copy, never stored
+    I.x[0] = p.x;
+    I.y[0] = p.y;
+    I.z[0] = p.z;
+    I.kx[0] = T(8.0 / 3.0) * (T)p.svx;
+    I.ky[0] = T(8.0 / 3.0) * (T)p.svy;
+    I.kz[0] = T(8.0 / 3.0) * (T)p.svz;
+  }
+  const T eps2 = (T)sa.e.eps2;
+#pragma unroll
+  for (int f = 0; f < kNF; ++f) acc[f][0] = 0.0;
+  PairAcc<T, 1> A;
+  int j = q;
+  while (j < Ns) {
+    // FP32: partial sums over kTile of this lane's terms, then into FP64
+    const int jend = sizeof(T) == 4 ? min(Ns, j + kTile * Q) : Ns;
+    A.zero();
+    for (; j + Q < jend; j += 2 * Q) {
+      const Pk p0 = pk[j];
+      const Pk p1 = pk[j + Q];
+      pair_one<T, MODE_FUSED, 1, true>(p0, j, eps2, I, A);
+      pair_one<T, MODE_FUSED, 1, true>(p1, j + Q, eps2, I, A);
+    }
+    if (j < jend) {
+      pair_one<T, MODE_FUSED, 1, true>(pk[j], j, eps2, I, A);
+      j += Q;
+    }
+    acc_flush(A, acc);
+  }
+}
+
+// The pending update: the massive object's acceleration at stage sa.pstage
+// from that stage's rows (as k_bh_final), then its Runge-Kutta bookkeeping (as
+// rk4_update) on the state in bi.  Every thread ends with the result in out
+// and the state of this stage's evaluation in own; workgroup 0 stores out (and
+// the new step-start state after stage 3).
+__device__ __forceinline__ void stage_bh_update(const StageArgs& sa, const double (&prows)[7],
+                                                const double (&phrows)[3], const double (&bi)[18],
+                                                double (&out)[18], BhStage& own) {
+  const EpiArgs& a = sa.e;
+  double A0[3], V0, P[3], r[3];
+  bh_quantities<double>(a, prows, A0, V0, P);
+  rows_sum<3>(phrows, r);
+  const int ps = sa.pstage;
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double atc = A0[c] + a.lam * r[c];
+    finite = finite && isfinite(atc);
+    const double X = bi[c], V = bi[3 + c], vs = bi[9 + c], KX = bi[12 + c], KV = bi[15 + c];
+    const double xn = rk4_next(ps, a.dt, X, KX, vs);
+    const double vn = rk4_next(ps, a.dt, V, KV, atc);
+    if (ps < 3) {
+      out[c] = X;
+      out[3 + c] = V;
+      out[12 + c] = ps == 0 ? vs : KX + 2.0 * vs;
+      out[15 + c] = ps == 0 ? atc : KV + 2.0 * atc;
+    } else {
+      out[c] = xn;
+      out[3 + c] = vn;
+      out[12 + c] = 0.0;
+      out[15 + c] = 0.0;
+    }
+    out[6 + c] = xn;
+    out[9 + c] = vn;
+    own.x0[c] = xn;
+    own.X[c] = out[c];
+    own.KX[c] = out[12 + c];
+    own.v[c] = vn;
+  }
+  if (blockIdx.x == 0) {
+    const int t = threadIdx.x;
+    if (t == 0 && !finite) atomicOr(a.status, 1);
+#pragma unroll
+    for (int c = 0; c < 18; ++c)
+      if (t == c) sa.bhs_out[c] = out[c];
+    if (ps == 3) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (t == 32 + c) uniform_ptr(a.X)[c] = out[c];
+        if (t == 40 + c) uniform_ptr(a.V)[c] = out[3 + c];
+      }
+    }
+  }
+}
+
+template <typename T, int NS>
+__global__ __launch_bounds__(kBlock) void k_stage(StageArgs sa) {
+  static_assert(kBlock == 256 && 64 % NS == 0 && NS * kNF <= kBlock, "stars per workgroup");
+  __shared__ double red[kNF * 4 * NS];
+  __shared__ double lds[10 * kBlock];
+  __shared__ double fsum[kNF * NS];
+  const EpiArgs& a = sa.e;
+  const int t = threadIdx.x;
+  const bool pend = sa.mode != kStageFirst;
+  const bool eval = sa.mode != kStageFinal;
+  // reads first: the pending update's rows and state, this stage's rows
+  double prows[7], phrows[3], rows[7], bi[18];
+  if (pend) {
+    rows_load<7>(sa.prow, a.nbpro, 8, prows);
+    rows_load<3>(sa.phrow, a.nbpro, 4, phrows);
+#pragma unroll
+    for (int c = 0; c < 18; ++c) bi[c] = sa.bhs_in[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bi[c] = bi[6 + c] = a.X[c];
+      bi[3 + c] = bi[9 + c] = a.V[c];
+      bi[12 + c] = bi[15 + c] = 0.0;
+    }
+  }
+  if (eval) {
+    rows_load<7>(a.bpart, a.nbpro, 8, rows);
+    double acc[kNF][1];
+    stage_sweep<T, NS>(sa, acc);
+    // a star's lanes within a wavefront are NS apart: an xor butterfly over
+    // distances NS ... 32 sums them (the same bits in each), and lane sl < NS
+    // of wavefront w parks star sl's partial
+#pragma unroll
+    for (int m = NS; m < 64; m <<= 1) {
+#pragma unroll
+      for (int f = 0; f < kNF; ++f) acc[f][0] += __shfl_xor(acc[f][0], m, 64);
+    }
+    if ((t & 63) < NS) {
+#pragma unroll
+      for (int f = 0; f < kNF; ++f) red[(f * 4 + (t >> 6)) * NS + (t & 63)] = acc[f][0];
+    }
+  }
+  BhStage own;
+  if (pend) {
+    double out[18];
+    stage_bh_update(sa, prows, phrows, bi, out, own);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      own.x0[c] = own.X[c] = bi[c];
+      own.KX[c] = 0.0;
+      own.v[c] = bi[3 + c];
+    }
+    if (blockIdx.x == 0) {
+#pragma unroll
+      for (int c = 0; c < 18; ++c)
+        if (t == c) sa.bhs_out[c] = bi[c];
+    }
+  }
+  if (!eval) return;
+  __syncthreads();
+  if (t < NS * kNF) {  // star sl, field f: the four wavefronts' partials in order
+    const int sl = t % NS, f = t / NS;
+    fsum[f * NS + sl] = ((red[(f * 4) * NS + sl] + red[(f * 4 + 1) * NS + sl]) +
+                         red[(f * 4 + 2) * NS + sl]) + red[(f * 4 + 3) * NS + sl];
+  }
+  __syncthreads();
+  epilogue_rows<double, T, NS, true>(a, blockIdx.x, lds, fsum, rows, own);
+}
+
+// A call's first packets, u/b rows and block rows in the stage kernel's
+// layout (a block row per NS stars, reduced as its epilogue reduces them, so
+// that a run resumed from a saved state repeats the continuous run bit for bit).
+template <typename T, int NS>
+__global__ __launch_bounds__(kBlock) void k_stage_head(EpiArgs a) {
+  __shared__ double lds[7 * kBlock];
+  const int t = threadIdx.x, k = blockIdx.x * NS + t;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (t < NS && k < a.Ns) {
+    const int s = k + 1;
+    const double x0[3] = {a.pos[0], a.pos[1], a.pos[2]};
+    const double xs[3] = {a.pos[3 * s], a.pos[3 * s + 1], a.pos[3 * s + 2]};
+    const double vs[3] = {a.vel[3 * s], a.vel[3 * s + 1], a.vel[3 * s + 2]};
+    star_terms<T, double>(x0, xs, vs, a.mass[s], a.G, a.G * a.mass[0], a.eps2, a.pk_next,
+                          a.ub_next, k, v);
+  }
+  wave_sums<7>(v, lds);
+  if (t < 8) a.bpart_next[(size_t)blockIdx.x * 8 + t] = t < 7 ? lds[t * kBlock] : 0.0;
+  if (blockIdx.x == 0 && t == 0) {
+    const double M = a.mass[0];
+    if (!(M > 0.0) || !isfinite(M)) atomicOr(a.status, 2);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1334,9 +1611,8 @@ __global__ __launch_bounds__(kBlock) void k_diag_epi(DiagEpiArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_diag_final(DiagEpiArgs a) {
-  __shared__ double lds[9 * kBlock];
   double r[9];
-  reduce_rows<9>(a.dpart, a.ndpart, 10, lds, r);
+  reduce_rows<9>(a.dpart, a.ndpart, 10, r);
   if (threadIdx.x == 0) {
     const double M = a.mass[0];
     const double* v1 = a.vel;

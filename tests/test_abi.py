@@ -133,6 +133,40 @@ def test_batched_validation_without_device(lib):
                                None, 0) == EINVAL
 
 
+def test_stage_kernel_table_without_device(lib, monkeypatch):
+    """pn_set_stage_kernel / pn_query_stage_kernel are host-only: entries by
+    precision and size range (the first match wins), clearing, the PN_STAGE_NS
+    override, and argument checks."""
+    from paper_1801_07986_amd import _binding
+
+    EINVAL = -1
+    monkeypatch.delenv("PN_STAGE_NS", raising=False)
+    try:
+        assert lib.pn_set_stage_kernel(-1, 0, 0, 0) == 0
+        assert lib.pn_query_stage_kernel(0, 100) == 0 and lib.pn_query_stage_kernel(1, 100) == 0
+        assert lib.pn_set_stage_kernel(0, 2, 300, 4) == 0
+        assert lib.pn_set_stage_kernel(0, 301, 1000, 8) == 0
+        assert lib.pn_set_stage_kernel(0, 2, 5000, 16) == 0  # covered below 1001 by the first two
+        assert lib.pn_set_stage_kernel(1, 50, 60, 2) == 0
+        assert [lib.pn_query_stage_kernel(0, n) for n in (2, 300, 301, 1000, 1001, 5000, 5001)] == \
+            [4, 4, 8, 8, 16, 16, 0]
+        assert [lib.pn_query_stage_kernel(1, n) for n in (49, 50, 60, 61)] == [0, 2, 2, 0]
+        monkeypatch.setenv("PN_STAGE_NS", "2")
+        assert lib.pn_query_stage_kernel(0, 5001) == 2
+        monkeypatch.setenv("PN_STAGE_NS", "0")
+        assert lib.pn_query_stage_kernel(0, 100) == 0
+        monkeypatch.delenv("PN_STAGE_NS")
+        for args in ((2, 2, 10, 4), (0, 1, 10, 4), (0, 10, 9, 4), (0, 2, 10, 3), (0, 2, 10, 0),
+                     (0, 2, 10, 32)):
+            assert lib.pn_set_stage_kernel(*args) == EINVAL
+        assert lib.pn_query_stage_kernel(0, 1) == EINVAL
+        assert lib.pn_query_stage_kernel(2, 100) == EINVAL
+        assert lib.pn_set_stage_kernel(-1, 0, 0, 0) == 0
+        assert lib.pn_query_stage_kernel(0, 100) == 0
+    finally:
+        _binding.install_tuned_shapes()
+
+
 def test_batch_shape_without_device(lib):
     """pn_set_batch_shape / pn_query_batch_shape are host-only: the default
     rule (1 i per lane; a common split count giving ~16k sweep workgroups, at

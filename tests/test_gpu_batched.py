@@ -97,6 +97,7 @@ def step_alone_in_shape(pn, pos, vel, mass, c, eps, dt, steps, prec, ipt, ns):
 
     N = len(mass)
     pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
+    pn.pn_set_stage_kernel(-1, 0, 0, 0)  # the chained stages, whose sweep takes the shape
     pn.pn_set_shape(prec, N, N, ipt, 4, ns)
     try:
         P, V = dev(pos), dev(vel)

@@ -66,6 +66,7 @@ def test_every_shape(pn, system, shape, prec):
     pos, vel, mass, (rN, rphi, r1), (rp, rv), scale = system
     print(f"[case] shape {shape} precision {prec}", flush=True)
     pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
+    pn.pn_set_stage_kernel(-1, 0, 0, 0)  # the chained stages, whose sweep takes the shape
     pn.pn_set_shape(prec, 2, 1 << 30, *shape)
     try:
         assert tuple(pn.pn_query_shape(prec, N)[:2]) == shape[:2]
