@@ -238,16 +238,38 @@ __device__ __forceinline__ void block_sum(const double (&v)[K], double* lds) {
   }
 }
 
-// Sum over the 64 lanes of a wavefront by an xor butterfly (exchange
-// distances 32, 16, ..., 1).  Both lanes of every exchange add the same two
-// values, so every lane ends with the same bits, and no barrier is needed.
+// A double from another lane of the same row of 16 by a DPP move (two 32-bit
+// halves); CTRL: 0x141 lane i <- 7 - i within 8, 0x140 i <- 15 - i within 16,
+// 0xB1 / 0x4E (quad permutations) i <- i ^ 1 / i ^ 2.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, true);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wavefront by six exchanges: lane i with 7 - i
+// (within 8), i ^ 1, i ^ 2, 15 - i (within 16), i ^ 16, i ^ 32.  Both lanes
+// of every exchange add the same two values, so after each level the lanes it
+// joined hold the same bits, and at the end every lane holds the same sum; no
+// barrier.  The first four levels are DPP moves within a row, the last two
+// go through the LDS crossbar (ds_bpermute).
 template <int K>
 __device__ __forceinline__ void wave_allsum(double (&v)[K]) {
 #pragma unroll
-  for (int m = 32; m > 0; m >>= 1) {
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x141>(v[k]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], m, 64);
-  }
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0xB1>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x4E>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x140>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], 16, 64);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], 32, 64);
 }
 
 // Per-wavefront sums of K doubles per thread (wave_allsum), the sum of
