@@ -1290,12 +1290,13 @@ __global__ __launch_bounds__(kBlock) void k_pair_bh(PairArgs a, EpiArgs e) {
 }
 
 // ---------------------------------------------------------------------------
-// Small systems: one launch per Runge-Kutta stage.  Each kernel boundary of a
-// chained step costs several microseconds however little work the kernels
-// do, so below a few thousand bodies a stage is one kernel: a workgroup owns
-// NS stars and sums all their j in its own 256 lanes (lane sl + NS q takes
-// star sl and j = q, q + 256/NS, ...), reduces them in LDS in fixed order and
-// runs those stars' epilogue.  No other workgroup's partials are needed, so
+// Small systems: one launch per Runge-Kutta stage.  With a few hundred bodies
+// a stage is a chain of latencies (launch, loads, reductions, dependent FP64
+// arithmetic) rather than work, and one kernel per stage saves a launch and
+// the split partials' trip through memory: a workgroup owns NS stars and
+// sums all their j in its own 256 lanes (lane sl + NS q takes star sl and
+// j = q, q + 256/NS, ...), reduces them in fixed order (a butterfly within
+// each wavefront, then the four wavefronts) and runs those stars' epilogue.  No other workgroup's partials are needed, so
 // nothing waits across workgroups.  The massive object's update of the
 // previous stage needs every epilogue's rows; each workgroup computes it
 // itself from the rows the previous launch wrote (the same sums in the same
