@@ -7,9 +7,10 @@ err_i = |a_i - a_ref,i| for the total acceleration, s_i = sum_b G m_b / R_ib^2
 the summed magnitude of its Newtonian pair terms and kappa_i = s_i / |a_ref,i|
 its condition number.
 
-What FP32 pair arithmetic fixes: each pair term is rounded to a few units of
-2^-24 of itself, so err_i is a small multiple of 2^-24 s_i wherever a few
-close neighbours dominate s_i, and err_i / |a_i| grows with kappa_i.
+What FP32 pair arithmetic fixes: each pair term passes six to eight FP32
+roundings and carries about one unit of 2^-24 of itself, so err_i is a small
+multiple of 2^-24 s_i wherever a few close neighbours dominate s_i, and
+err_i / |a_i| grows with kappa_i.
 Checked here:
   * err_i <= 1e-6 max(|a_ref,i|, s_i / 2) on every body (the mixed bound of
     the parity tests: 1e-6 relative for kappa <= 2, 5e-7 s_i beyond);

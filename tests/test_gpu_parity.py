@@ -16,12 +16,11 @@ a symmetry point, e.g. the massive object between two stars placed opposite
 each other, has a_ref = 0 and only rounding is left on either side).  For the
 1PN part the floor is 1e-6 s.
 
-Mixed: F = 1/2 (MIXED_FLOOR).  Every FP32 pair term carries a rounding error
-of a few units of 2^-24 of itself (the FP32 difference, v_rsq_f32 to about
-one ulp, cubed, and the products), and one FP32 rounding of a single
-dominant term already costs 2^-24 kappa of the result: a per-body 1e-6 of
-|a| is out of reach of FP32 pair arithmetic for kappa above ~16, whatever
-the summation.  Measured over every body of 16 seeded Plummer systems
+Mixed: F = 1/2 (MIXED_FLOOR).  Every FP32 pair term passes six to eight
+FP32 roundings (the difference, r^2, v_rsq_f32 to about one ulp, the
+products, the tile sum) and carries about one unit of 2^-24 of itself, so a
+body's error is a small multiple of 2^-24 s when a few close terms dominate s,
+and its error relative to |a| grows with kappa.  Measured over every body of 16 seeded Plummer systems
 (N = 16384 and 65536), the error stays below 3.7e-7 s, while the plain
 relative error exceeds 1e-6 at 1-3 bodies per system in 5 of them, all with
 kappa >= 9.  The mixed bound is therefore 1e-6 of |a| for kappa <= 2 and
