@@ -272,22 +272,14 @@ __device__ __forceinline__ void wave_allsum(double (&v)[K]) {
   for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], 32, 64);
 }
 
-// Per-wavefront sums of K doubles per thread (wave_allsum), the sum of
-// wavefront w in lds[k*kBlock + 64 w] after one barrier.  The prologue (a row
-// per wavefront) and the epilogues (their stars in wavefront 0) reduce their
-// massive-object rows this way, so that a row holds the same sum whichever
-// kernel wrote it.
+// Element col of a register array, chosen per lane without indexing the
+// array at run time (a chain of selects).
 template <int K>
-__device__ __forceinline__ void wave_sums(const double (&v)[K], double* lds) {
-  double s[K];
+__device__ __forceinline__ double pick(const double (&v)[K], int col) {
+  double r = 0.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) s[k] = v[k];
-  wave_allsum<K>(s);
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) lds[k * kBlock + threadIdx.x] = s[k];
-  }
-  __syncthreads();
+  for (int k = 0; k < K; ++k) r = col == k ? v[k] : r;
+  return r;
 }
 
 // Wave index as a scalar (so that loop bounds derived from it stay uniform
@@ -393,7 +385,7 @@ __device__ __forceinline__ void star_terms(const S (&x0)[3], const S (&xs)[3], c
 
 // W = Width<T>::n doubles per quantity (value, and derivative for Dual).
 template <typename T>
-__device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double* lds) {
+__device__ __forceinline__ void prologue_block(const ProArgs& a, int blk) {
   using S = typename ScalarOf<T>::type;
   constexpr int W = Width<T>::n;
   const int k = blk * kBlock + threadIdx.x;
@@ -412,16 +404,17 @@ __device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double
     }
     star_terms<T, S>(x0, xs, vs, a.mass[s], a.G, a.G * a.mass[0], a.eps2, a.pk, a.ub, k, v);
   }
+  // a block row per wavefront (64 stars), summed by wave_allsum and written
+  // from the wavefront's own registers
   double flat[7 * W];
 #pragma unroll
   for (int q = 0; q < 7; ++q) put(flat, q, 7, v[q]);
-  wave_sums<7 * W>(flat, lds);
+  wave_allsum<7 * W>(flat);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (l < 8 * W) {
     // row layout: value columns 0..7, derivative columns 8..15 (Dual)
     const int q = l & 7, h = l >> 3;
-    a.bpart[((size_t)blk * kProRows + w) * 8 * W + l] =
-        q < 7 ? lds[(h * 7 + q) * kBlock + 64 * w] : 0.0;
+    a.bpart[((size_t)blk * kProRows + w) * 8 * W + l] = q < 7 ? pick(flat, h * 7 + q) : 0.0;
   }
   if (blk == 0 && threadIdx.x == 0) {
     const double M = a.mass[0];
@@ -431,8 +424,7 @@ __device__ __forceinline__ void prologue_block(const ProArgs& a, int blk, double
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prologue(ProArgs a) {
-  __shared__ double lds[7 * Width<T>::n * kBlock];
-  prologue_block<T>(a, blockIdx.x, lds);
+  prologue_block<T>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1160,19 +1152,24 @@ __device__ __forceinline__ void epilogue_rows(const EpiArgs& a, int blk, double*
 #pragma unroll
     for (int q = 0; q < NP; ++q) bhs[3 + q] = pro[q];
   }
-  wave_sums<NB>(bhs, lds);  // the stars are in wavefront 0
-  if (threadIdx.x < 4 * W) {
-    // row layout: values in columns 0..2, derivatives in 4..6 (Dual)
-    const int q = threadIdx.x & 3, h = threadIdx.x >> 2;
-    a.bhpart[(size_t)blk * 4 * W + threadIdx.x] = q < 3 ? lds[(h * 3 + q) * kBlock] : 0.0;
-  }
-  if constexpr (CHAIN) {
-    // the prologue's row layout: sum m b (3), sum m u, sum m v (3), 0 (and
-    // the same 8 columns of derivatives for the jerk sweep)
-    constexpr int RW = JNEXT ? 16 : 8;
-    if (threadIdx.x >= 64 && threadIdx.x < 64 + RW) {
-      const int c = threadIdx.x - 64, q = c & 7, h = c >> 3;
-      a.bpart_next[(size_t)blk * RW + c] = q < 7 ? lds[(3 + h * 7 + q) * kBlock] : 0.0;
+  // the stars are in wavefront 0: it sums its rows (wave_allsum, every lane
+  // then holds every sum) and writes them from its registers
+  if (wave_id() == 0) {
+    wave_allsum<NB>(bhs);
+    const int l = threadIdx.x;
+    if (l < 4 * W) {
+      // row layout: values in columns 0..2, derivatives in 4..6 (Dual)
+      const int q = l & 3, h = l >> 2;
+      a.bhpart[(size_t)blk * 4 * W + l] = q < 3 ? pick(bhs, h * 3 + q) : 0.0;
+    }
+    if constexpr (CHAIN) {
+      // the prologue's row layout: sum m b (3), sum m u, sum m v (3), 0 (and
+      // the same 8 columns of derivatives for the jerk sweep)
+      constexpr int RW = JNEXT ? 16 : 8;
+      if (l >= 32 && l < 32 + RW) {
+        const int c = l - 32, q = c & 7, h = c >> 3;
+        a.bpart_next[(size_t)blk * RW + c] = q < 7 ? pick(bhs, 3 + h * 7 + q) : 0.0;
+      }
     }
   }
 }
@@ -1494,7 +1491,6 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs sa) {
 // that a run resumed from a saved state repeats the continuous run bit for bit).
 template <typename T, int NS>
 __global__ __launch_bounds__(kBlock) void k_stage_head(EpiArgs a) {
-  __shared__ double lds[7 * kBlock];
   const int t = threadIdx.x, k = blockIdx.x * NS + t;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   if (t < NS && k < a.Ns) {
@@ -1505,8 +1501,10 @@ __global__ __launch_bounds__(kBlock) void k_stage_head(EpiArgs a) {
     star_terms<T, double>(x0, xs, vs, a.mass[s], a.G, a.G * a.mass[0], a.eps2, a.pk_next,
                           a.ub_next, k, v);
   }
-  wave_sums<7>(v, lds);
-  if (t < 8) a.bpart_next[(size_t)blockIdx.x * 8 + t] = t < 7 ? lds[t * kBlock] : 0.0;
+  if (t < 64) {  // the stars are in wavefront 0 (as in the stage's epilogue)
+    wave_allsum<7>(v);
+    if (t < 8) a.bpart_next[(size_t)blockIdx.x * 8 + t] = t < 7 ? pick(v, t) : 0.0;
+  }
   if (blockIdx.x == 0 && t == 0) {
     const double M = a.mass[0];
     if (!(M > 0.0) || !isfinite(M)) atomicOr(a.status, 2);
@@ -2052,10 +2050,9 @@ __device__ __forceinline__ EpiArgs batch_epi_args(const BatchArgs& b, const SysD
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prologue_batched(BatchArgs b) {
-  __shared__ double lds[7 * kBlock];
   const int r = batch_rank(b.pre, b.n_sys, blockIdx.x);
   const SysDev S = b.sys[b.order[r]];
-  prologue_block<T>(batch_pro_args<T>(b, S), blockIdx.x - b.pre[r], lds);
+  prologue_block<T>(batch_pro_args<T>(b, S), blockIdx.x - b.pre[r]);
 }
 
 // IPT i-bodies per lane for every system of the ensemble (the plan's shape)
