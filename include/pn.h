@@ -295,6 +295,8 @@ const char* pn_strerror(int code);
 /*
  * After a call made with PN_TIMING: out (HOST, 3 doubles) receives
  * [number of pair-kernel launches, their total duration in ms, pairs per launch].
+ * A pn_step in one-launch stages (pn_set_stage_kernel) times those stage
+ * kernels, which also run the epilogue.
  */
 int pn_last_timing(double* out);
 
