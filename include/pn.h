@@ -29,9 +29,10 @@
  * - Ownership: the caller owns every argument buffer.  The library owns only
  *   internal scratch, kept per device and grown on demand, and (pn_step) cached
  *   HIP graphs; pn_release() frees both.  No argument pointer is kept after the
- *   call returns, except inside the cached step graph of pn_step,
- *   pn_step_hermite and pn_step_batched, which is re-captured when any pointer
- *   or parameter changes.
+ *   call returns, except inside the cached step graphs of pn_step,
+ *   pn_step_hermite (one step, and 16 steps per replay for long runs) and
+ *   pn_step_batched, which are re-captured when any pointer or parameter
+ *   changes.
  * - Return codes: PN_OK, or one of the negative codes below.  No C++ exception
  *   crosses the ABI.  Outputs are unspecified after an error, except
  *   PN_ENONFINITE, where all outputs are written.

@@ -69,9 +69,34 @@ enum PairMode { MODE_P1 = 1, MODE_P2 = 2, MODE_FUSED = 3 };
 // scaled, s = sqrt(3/2) v: then 3/2 (x.v_j / R)^2 = (x.s_j / R)^2, and with
 // the per-i vector (4/sqrt(3/2)) v_i the other velocity products come out
 // unscaled (4 v_i.v_j = [(4/sqrt(3/2)) v_i].s_j); D'_ij / sqrt(3/2) is
-// accumulated and rescaled in the epilogue.
+// accumulated and rescaled in the epilogue.  The FP64 packet holds s/2 (see
+// PairScale below).
 constexpr double kSqrt32 = 1.22474487139158904909864203735;    // sqrt(3/2)
 constexpr double kInvSqrt32 = 0.816496580927726032732428024902; // 1/sqrt(3/2)
+
+// Scalings of the pair sweep.  The FP64 sweep refines v_rsq_f64 by a Newton
+// step written Y = y (3 - x y^2), which is 2/R (three instructions; the form
+// that yields 1/R takes four), and carries the factor 2 through instead of
+// removing it: its packets hold s/2, its i-vector is 2 (4/sqrt(3/2)) v_i, the
+// D-term coefficient is -8, and a wavefront's sums come out as 2U, 8G, 8Q,
+// 16 C2 and 2 Q7, scaled back when it flushes them.  Every factor is a power
+// of two, so the FP64 sums are those of the unscaled terms bit for bit except
+// for the reciprocal square root itself.  The FP32 and dual-number sweeps use
+// 1/R as it is.
+template <typename T> struct PairScale {
+  static constexpr double sv = kSqrt32;         // packet velocity = sv v
+  static constexpr double inv_sv = kInvSqrt32;  // v = inv_sv (packet velocity)
+  static constexpr double k = 8.0 / 3.0;        // i-vector = k (packet velocity)
+  static constexpr double d = -2.0;             // D term: d (x.s_j) + x.k_i
+  static constexpr double u = 1.0, g = 1.0, q = 1.0, c2 = 1.0, q7 = 1.0;  // flush factors
+};
+template <> struct PairScale<double> {
+  static constexpr double sv = 0.5 * kSqrt32;
+  static constexpr double inv_sv = 2.0 * kInvSqrt32;
+  static constexpr double k = 32.0 / 3.0;
+  static constexpr double d = -8.0;
+  static constexpr double u = 0.5, g = 0.125, q = 0.125, c2 = 0.0625, q7 = 0.5;
+};
 
 struct alignas(16) PkF64 {
   double x, y, z, gm, svx, svy, svz, e, hbx, hby, hbz, pad;
@@ -95,10 +120,11 @@ template <> struct PkOf<float> { using type = PkF32; };
 // brings it to full double precision (residual ~ (5/16) r^3 < 2^-70).  The
 // O(N) kernels (massive-object terms, epilogues) use this.
 //
-// The O(N^2) pair sweeps use one Newton step instead, one instruction less
-// per pair: y (1 + e) becomes y (1 + r/2) = y (1 - 3/2 e^2 - e^3/2), at most
-// 4.1e-15 below the true value (the sweep's accuracy target is 1e-12;
-// measured per-body errors stay at 1e-14).
+// The O(N^2) pair sweeps use one Newton step instead: y (1 + e) becomes
+// y (1 + r/2) = y (1 - 3/2 e^2 - e^3/2), at most 4.1e-15 below the true value
+// (the sweep's accuracy target is 1e-12; measured per-body errors stay at
+// 1e-14).  Written y (3 - x y^2) it is twice that in three instructions, two
+// fewer than the series.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double rsqrt_f64(double x) {
   double y = __builtin_amdgcn_rsq(x);
@@ -110,6 +136,11 @@ __device__ __forceinline__ double rsqrt_f64_newton(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double r = fma(-x * y, y, 1.0);
   return fma(y * r, 0.5, y);
+}
+// The same Newton step as 2/sqrt(x) = y (3 - x y^2): one instruction less.
+__device__ __forceinline__ double rsqrt2_f64_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-x * y, y, 3.0);
 }
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt_f64(x); }
@@ -165,9 +196,10 @@ __device__ __forceinline__ Dual rsqrt_t(Dual x) {
   const double y = rsqrt_f64(x.v);
   return {y, -0.5 * y * y * y * x.d};
 }
-// the pair sweep's reciprocal square root (FP64: one Newton step, see rsqrt_f64)
+// the pair sweep's reciprocal square root (FP64: one Newton step, see rsqrt_f64,
+// and 2/R rather than 1/R, see PairScale)
 __device__ __forceinline__ float rsqrt_pair(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_pair(double x) { return rsqrt_f64_newton(x); }
+__device__ __forceinline__ double rsqrt_pair(double x) { return rsqrt2_f64_newton(x); }
 __device__ __forceinline__ Dual rsqrt_pair(Dual x) {
   const double y = rsqrt_f64_newton(x.v);
   return {y, -0.5 * y * y * y * x.d};
@@ -360,9 +392,9 @@ __device__ __forceinline__ void star_terms(const S (&x0)[3], const S (&xs)[3], c
   p.y = xs[1];
   p.z = xs[2];
   p.gm = (T)(G * m);
-  p.svx = (T)(kSqrt32 * vx);
-  p.svy = (T)(kSqrt32 * vy);
-  p.svz = (T)(kSqrt32 * vz);
+  p.svx = (T)(PairScale<T>::sv * vx);
+  p.svy = (T)(PairScale<T>::sv * vy);
+  p.svz = (T)(PairScale<T>::sv * vz);
   p.e = (T)fma(S(-2.0), v2, u);
   p.hbx = (T)(-0.5 * bx);
   p.hby = (T)(-0.5 * by);
@@ -495,7 +527,7 @@ __device__ __forceinline__ void pair_one(const typename PkOf<T>::type& p, int j,
       s = fma(I.kz[ii], sz, fma(I.ky[ii], sy, fma(I.kx[ii], sx, s)));  // + 4 v_i.v_j
       s = fma(dz, (T)p.hbz, fma(dy, (T)p.hby, fma(dx, (T)p.hbx, s)));  // - x.b_j / 2
       const T x4 = fma(dz, I.kz[ii], fma(dy, I.ky[ii], dx * I.kx[ii]));
-      const T D = fma(T(-2), xs, x4);              // x.(4 v_i - 3 v_j) / sqrt(3/2)
+      const T D = fma(T(PairScale<T>::d), xs, x4);  // x.(4 v_i - 3 v_j) / sqrt(3/2)
       const T c1 = mr3 * s, c2 = mr3 * D;
       A.Qx[ii] = fma(-c2, sx, fma(c1, dx, A.Qx[ii]));
       A.Qy[ii] = fma(-c2, sy, fma(c1, dy, A.Qy[ii]));
@@ -540,36 +572,39 @@ __device__ __forceinline__ void pair_segment(const typename PkOf<T>::type* __res
   }
 }
 
-// acc[f] += x (and acc[kNF + f] += dx/dt for Dual)
+// acc[f] += s x (and acc[kNF + f] += s dx/dt for Dual); s is a PairScale
+// factor, a power of two (1 outside the FP64 sweep)
 template <int NFO, int IPT>
-__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, float x) {
-  acc[f][ii] += (double)x;
+__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, float x, double s) {
+  acc[f][ii] += (double)x * s;
 }
 template <int NFO, int IPT>
-__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, double x) {
-  acc[f][ii] += x;
+__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, double x,
+                                        double s) {
+  acc[f][ii] += x * s;
 }
 template <int NFO, int IPT>
-__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, Dual x) {
-  acc[f][ii] += x.v;
-  acc[kNF + f][ii] += x.d;
+__device__ __forceinline__ void acc_add(double (&acc)[NFO][IPT], int f, int ii, Dual x, double s) {
+  acc[f][ii] += x.v * s;
+  acc[kNF + f][ii] += x.d * s;
 }
 
 template <typename T, int IPT, int NFO>
 __device__ __forceinline__ void acc_flush(const PairAcc<T, IPT>& A, double (&acc)[NFO][IPT]) {
 #pragma unroll
   for (int ii = 0; ii < IPT; ++ii) {
-    acc_add(acc, F_U, ii, A.U[ii]);
-    acc_add(acc, F_G, ii, A.Gx[ii]);
-    acc_add(acc, F_G + 1, ii, A.Gy[ii]);
-    acc_add(acc, F_G + 2, ii, A.Gz[ii]);
-    acc_add(acc, F_Q, ii, A.Qx[ii]);
-    acc_add(acc, F_Q + 1, ii, A.Qy[ii]);
-    acc_add(acc, F_Q + 2, ii, A.Qz[ii]);
-    acc_add(acc, F_C2, ii, A.C2[ii]);
-    acc_add(acc, F_Q7, ii, A.Q7x[ii]);
-    acc_add(acc, F_Q7 + 1, ii, A.Q7y[ii]);
-    acc_add(acc, F_Q7 + 2, ii, A.Q7z[ii]);
+    using SC = PairScale<T>;
+    acc_add(acc, F_U, ii, A.U[ii], SC::u);
+    acc_add(acc, F_G, ii, A.Gx[ii], SC::g);
+    acc_add(acc, F_G + 1, ii, A.Gy[ii], SC::g);
+    acc_add(acc, F_G + 2, ii, A.Gz[ii], SC::g);
+    acc_add(acc, F_Q, ii, A.Qx[ii], SC::q);
+    acc_add(acc, F_Q + 1, ii, A.Qy[ii], SC::q);
+    acc_add(acc, F_Q + 2, ii, A.Qz[ii], SC::q);
+    acc_add(acc, F_C2, ii, A.C2[ii], SC::c2);
+    acc_add(acc, F_Q7, ii, A.Q7x[ii], SC::q7);
+    acc_add(acc, F_Q7 + 1, ii, A.Q7y[ii], SC::q7);
+    acc_add(acc, F_Q7 + 2, ii, A.Q7z[ii], SC::q7);
   }
 }
 
@@ -607,10 +642,10 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp, do
     I.x[ii] = p.x;
     I.y[ii] = p.y;
     I.z[ii] = p.z;
-    // (4/sqrt(3/2)) v_i = (8/3) s_i
-    I.kx[ii] = T(8.0 / 3.0) * (T)p.svx;
-    I.ky[ii] = T(8.0 / 3.0) * (T)p.svy;
-    I.kz[ii] = T(8.0 / 3.0) * (T)p.svz;
+    // (4/sqrt(3/2)) v_i = (8/3) s_i (times 2 in FP64, see PairScale)
+    I.kx[ii] = T(PairScale<T>::k) * (T)p.svx;
+    I.ky[ii] = T(PairScale<T>::k) * (T)p.svy;
+    I.kz[ii] = T(PairScale<T>::k) * (T)p.svz;
   }
   // j-range of this wavefront
   int j0 = sp * a.jchunk;
@@ -1334,9 +1369,9 @@ __device__ __forceinline__ void stage_sweep(const StageArgs& sa, double (&acc)[k
     I.x[0] = p.x;
     I.y[0] = p.y;
     I.z[0] = p.z;
-    I.kx[0] = T(8.0 / 3.0) * (T)p.svx;
-    I.ky[0] = T(8.0 / 3.0) * (T)p.svy;
-    I.kz[0] = T(8.0 / 3.0) * (T)p.svz;
+    I.kx[0] = T(PairScale<T>::k) * (T)p.svx;
+    I.ky[0] = T(PairScale<T>::k) * (T)p.svy;
+    I.kz[0] = T(PairScale<T>::k) * (T)p.svz;
   }
   const T eps2 = (T)sa.e.eps2;
 #pragma unroll
@@ -1534,7 +1569,8 @@ __global__ __launch_bounds__(kBlock) void k_diag_pair(DiagPairArgs a) {
   const int i = ilo + threadIdx.x;
   const PkF64& pi = pk[min(i, a.Ns - 1)];
   const double xi = pi.x, yi = pi.y, zi = pi.z;
-  const double vxi = kInvSqrt32 * pi.svx, vyi = kInvSqrt32 * pi.svy, vzi = kInvSqrt32 * pi.svz;
+  constexpr double iv = PairScale<double>::inv_sv;
+  const double vxi = iv * pi.svx, vyi = iv * pi.svy, vzi = iv * pi.svz;
   const int j0 = blockIdx.y * a.jchunk, j1 = min(a.Ns, j0 + a.jchunk);
   double U = 0.0, W = 0.0, Yx = 0.0, Yy = 0.0, Yz = 0.0;
   for (int j = j0; j < j1; ++j) {
@@ -1544,7 +1580,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_pair(DiagPairArgs a) {
     if (j >= ilo && j < ihi) rinv = (j == i) ? 0.0 : rinv;
     const double mr = p.gm * rinv;
     const double rinv2 = rinv * rinv;
-    const double vxj = kInvSqrt32 * p.svx, vyj = kInvSqrt32 * p.svy, vzj = kInvSqrt32 * p.svz;
+    const double vxj = iv * p.svx, vyj = iv * p.svy, vzj = iv * p.svz;
     const double vv = fma(vzi, vzj, fma(vyi, vyj, vxi * vxj));
     const double xvi = fma(dz, vzi, fma(dy, vyi, dx * vxi));
     const double xvj = fma(dz, vzj, fma(dy, vyj, dx * vxj));
@@ -1863,9 +1899,9 @@ __global__ __launch_bounds__(kBlock) void k_eih_packets(EihArgs a) {
     p.y = a.pos[3 * b + 1];
     p.z = a.pos[3 * b + 2];
     p.gm = (T)(a.G * a.mass[b]);
-    p.svx = (T)(kSqrt32 * a.vel[3 * b]);
-    p.svy = (T)(kSqrt32 * a.vel[3 * b + 1]);
-    p.svz = (T)(kSqrt32 * a.vel[3 * b + 2]);
+    p.svx = (T)(PairScale<T>::sv * a.vel[3 * b]);
+    p.svy = (T)(PairScale<T>::sv * a.vel[3 * b + 1]);
+    p.svz = (T)(PairScale<T>::sv * a.vel[3 * b + 2]);
     p.e = T(0);
     p.hbx = T(0);
     p.hby = T(0);

@@ -225,6 +225,18 @@ def test_hermite_graph_equals_direct_launches(pn):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+def test_hermite_long_graph_equals_direct_launches(pn):
+    """35 steps: two replays of the 16-step graph and three of the one-step
+    graph, bitwise the same as direct launches."""
+    pos, vel, mass = case(777, 908)
+    outs = []
+    for flags in (0, pn.PN_NOGRAPH):
+        P, V = dev(pos), dev(vel)
+        pn.pn_step_hermite(P, V, dev(mass), G, 40.0, 1e-4, 1e-4, 35, flags=flags)
+        outs.append((host(P), host(V)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_hermite_zero_is_noop_and_rk4_graph_survives(pn):
     pos, vel, mass = case(100, 907)
     P, V = dev(pos), dev(vel)

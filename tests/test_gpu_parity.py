@@ -273,6 +273,22 @@ def test_step_graph_equals_direct_launches(pn):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_step_long_graph_equals_direct_launches(pn, prec):
+    """40 steps replay the 16-step graph twice and the one-step graph seven
+    times; the same as 40 direct steps, and as 17 + 23 steps, bit for bit."""
+    pos, vel, mass = case(777, 19)
+    outs = []
+    for flags, parts in ((0, (40,)), (pn.PN_NOGRAPH, (40,)), (0, (17, 23))):
+        P, V = dev(pos), dev(vel)
+        for n in parts:
+            pn.pn_step(P, V, dev(mass), G, 40.0, 1e-4, 1e-4, n, prec, flags=flags)
+        outs.append((host(P), host(V)))
+    same = [np.array_equal(outs[0][0], o[0]) and np.array_equal(outs[0][1], o[1]) for o in outs[1:]]
+    print(f"prec={prec}: graph = direct {same[0]}, 40 = 17 + 23 {same[1]}")
+    assert all(same)
+
+
 def test_step_zero_is_noop(pn):
     pos, vel, mass = case(100, 17)
     P, V = dev(pos), dev(vel)

@@ -125,6 +125,21 @@ def test_stage_bitwise(pn, stage, N, ns, prec):
     assert same(a, b) and same(a, d) and same(a, r) and same(a, s)
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_stage_long_graph_bitwise(pn, stage, prec):
+    """41 steps: the first direct, then two replays of the 16-step graph and
+    eight of the one-step graph; the same as direct launches and as 20 + 21."""
+    stage(4)
+    pos, vel, mass = inputs.plummer_bh(100, 0.1, 8)
+    a = step(pn, pos, vel, mass, 41, prec)
+    d = step(pn, pos, vel, mass, 41, prec, flags=pn.PN_NOGRAPH)
+    p2, v2 = step(pn, pos, vel, mass, 20, prec)
+    r = step(pn, p2, v2, mass, 21, prec)
+    same = lambda x, y: np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])  # noqa: E731
+    print(f"prec={prec}: direct {same(a, d)}, 20 + 21 {same(a, r)}")
+    assert same(a, d) and same(a, r)
+
+
 def test_stage_device_checks(pn, stage):
     stage(4)
     pos, vel, mass = inputs.plummer_bh(64, 0.1, 14)
