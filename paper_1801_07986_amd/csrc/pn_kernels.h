@@ -323,12 +323,20 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // thread of every workgroup ends with the same bits, without a barrier.
 // Split in two so that a kernel can request the rows of several sums before
 // waiting for any: rows_load (this lane's partial sums), then rows_sum.
+// The lane's first row is loaded, not added, so that up to 64 rows (every
+// system of up to 4096 stars) rows_load issues its loads and returns without
+// waiting for them.
 template <int K>
 __device__ __forceinline__ void rows_load(const double* part, int rows, int stride,
                                           double (&v)[K]) {
+  const int l = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = 0.0;
-  for (int r = threadIdx.x & 63; r < rows; r += 64) {
+  if (l < rows) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = part[(size_t)l * stride + k];
+  }
+  for (int r = l + 64; r < rows; r += 64) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += part[(size_t)r * stride + k];
   }
@@ -959,7 +967,7 @@ __device__ __forceinline__ void epilogue_rows(const EpiArgs& a, int blk, double*
   const int i = k + 1;
   S ui = 0.0, bx = 0.0, by = 0.0, bz = 0.0, xi = 0.0, yi = 0.0, zi = 0.0;
   S vi[3] = {0.0, 0.0, 0.0};
-  double gm_s = 0.0;
+  double m_s = 0.0;  // the star's mass (G m is formed where it is used, after the loads)
   Rk4In rk[3];
   // the massive object's step-start position, stage sum and velocity (uniform:
   // scalar loads)
@@ -992,7 +1000,7 @@ __device__ __forceinline__ void epilogue_rows(const EpiArgs& a, int blk, double*
       vi[0] = ld<S>(a.vel, a.vel_d, 3 * i);
       vi[1] = ld<S>(a.vel, a.vel_d, 3 * i + 1);
       vi[2] = ld<S>(a.vel, a.vel_d, 3 * i + 2);
-      gm_s = a.G * a.mass[i];
+      m_s = a.mass[i];
     }
     if constexpr (!DUAL) {
       for (int c = 0; c < 3; ++c) rk[c] = rk4_load(a, 3 * (size_t)i + c);
@@ -1114,6 +1122,7 @@ __device__ __forceinline__ void epilogue_rows(const EpiArgs& a, int blk, double*
       }
       // this star's term of the massive object's 1PN sum (Eqs. (2)-(3))
       const S Vs = Vphi;
+      const double gm_s = a.G * m_s;
       const S ks = gm_s * rinv0 * rinv0;
       const S n0s[3] = {-n0[0], -n0[1], -n0[2]};
       const S d0s[3] = {-d0[0], -d0[1], -d0[2]};
