@@ -51,12 +51,10 @@ PEAK_FP32_VALU = 157.3e12
 # Keyed by (workload, kernel, j-splits): the launch shape comes from the tuned
 # table, so a figure applies only to the kernel and split count it was taken on.
 TRAFFIC_BYTES = {
-    # FETCH 6356.50 KiB, WRITE 34582.05 KiB per launch
-    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,4>", 24): 48430139,
-    # FETCH 6311.80 KiB, WRITE 46109.37 KiB per launch
-    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,4>", 32): 60142551,
-    # FETCH 79871.75 KiB, WRITE 188669.37 KiB per launch
-    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 32): 356774769,
+    # FETCH 6356.73 KiB, WRITE 34582.1 KiB per launch
+    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,4>", 24): 48430653,
+    # FETCH 79974.3 KiB, WRITE 188669 KiB per launch
+    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 32): 356984422,
 }
 
 
