@@ -236,6 +236,9 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "tuned_shapes.json"))
     ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--sizes", default=None,
+                    help="comma-separated N: re-tune these sizes only, keeping the table's "
+                         "other entries (ranges are recomputed over all measured sizes)")
     ap.add_argument("--batched", action="store_true",
                     help="tune pn_step_batched's shape only (kept with the existing table)")
     ap.add_argument("--stage", action="store_true",
@@ -255,7 +258,15 @@ def main(argv=None):
         table["stage"] = tune_stage(log=log)
         table["stage_created"] = time.strftime("%Y-%m-%d %H:%M:%S")
     else:
-        table = to_table(tune(QUICK_SIZES if args.quick else SIZES, log=log))
+        if args.sizes:
+            sizes = sorted({int(s) for s in args.sizes.split(",")})
+            kept = [dict(N=e["measured_N"], precision=e["precision"], ipt=e["ipt"], ws=e["ws"],
+                         nsplit=e["nsplit"], step_ms=e["step_ms"],
+                         default_step_ms=e["default_step_ms"])
+                    for e in old.get("entries", []) if e["measured_N"] not in sizes]
+            table = to_table(kept + tune(sizes, log=log))
+        else:
+            table = to_table(tune(QUICK_SIZES if args.quick else SIZES, log=log))
         for key in ("batched", "stage"):
             if key in old:
                 table[key] = old[key]
