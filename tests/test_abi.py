@@ -278,3 +278,41 @@ def test_table32_oracle_leg_runs_the_protocol():
     assert np.isfinite(r["std_s"])
     r = bench.oracle_table32(oracle, pos, vel, mass, samples=3, budget_s=0.0)
     assert r["runs"] == 0 and r["kind"].startswith("extrapolated") and r["std_s"] is None
+
+
+def test_autotune_partial_retune_keeps_other_entries(tmp_path, monkeypatch):
+    """autotune --sizes: the re-tuned sizes replace their entries, the others
+    are kept, and the ranges are those of a full run over the union of sizes
+    (host logic; the timing is replaced by a stub)."""
+    import json
+
+    from paper_1801_07986_amd import autotune
+
+    src = os.path.join(ROOT, "paper_1801_07986_amd", "tuned_shapes.json")
+    with open(src) as f:
+        old = json.load(f)
+    out = tmp_path / "t.json"
+    out.write_text(json.dumps(old))
+
+    def fake_tune(sizes, log=print):
+        return [dict(N=N, precision=p, ipt=2, ws=1, nsplit=7, step_ms=1.0, default_step_ms=2.0)
+                for N in sizes for p in ("fp64", "mixed")]
+
+    monkeypatch.setattr(autotune, "tune", fake_tune)
+    autotune.main(["--sizes", "1024,5000", "--out", str(out)])
+    new = json.loads(out.read_text())
+    assert new["stage"] == old["stage"] and new["batched"] == old["batched"]
+    for prec in ("fp64", "mixed"):
+        e_old = [e for e in old["entries"] if e["precision"] == prec]
+        e_new = [e for e in new["entries"] if e["precision"] == prec]
+        assert [e["measured_N"] for e in e_new] == sorted(
+            {e["measured_N"] for e in e_old if e["measured_N"] != 1024} | {1024, 5000})
+        for e in e_new:
+            if e["measured_N"] in (1024, 5000):
+                assert (e["ipt"], e["ws"], e["nsplit"]) == (2, 1, 7)
+            else:
+                o = next(x for x in e_old if x["measured_N"] == e["measured_N"])
+                assert (e["ipt"], e["ws"], e["nsplit"]) == (o["ipt"], o["ws"], o["nsplit"])
+        # ranges tile [2, 2^28] without gaps or overlaps
+        assert e_new[0]["n_min"] == 2 and e_new[-1]["n_max"] == 1 << 28
+        assert all(a["n_max"] + 1 == b["n_min"] for a, b in zip(e_new, e_new[1:]))
