@@ -275,7 +275,8 @@ int pn_query_stage_kernel(int precision, int64_t N);
  * Launch shape of the star-star sweep for systems with n_min <= N <= n_max in
  * the given precision (searched by the autotuner; later entries never override
  * earlier ones that match).  ipt: i-bodies per lane (1 or 2); ws: wavefronts
- * sharing one i-range (1 or 4); nsplit: j-range splits (0 = default rule).
+ * sharing one i-range (1, 4, or 8 in workgroups of 512 threads); nsplit: j-range
+ * splits (0 = default rule).
  * precision < 0 clears the table.  Shapes change speed only: results of a
  * given shape are deterministic and every shape meets the same accuracy.
  */

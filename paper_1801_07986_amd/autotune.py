@@ -6,7 +6,7 @@ wall clock around a run of steps on the caller's stream) over the candidate
 shapes
 
     ipt in {1, 2}   i-bodies per lane
-    ws in {1, 4}    wavefronts sharing one i-range
+    ws in {1, 4, 8} wavefronts sharing one i-range (8: workgroups of 512 threads)
     nsplit          j-range splits (at least 4 j per wavefront, or 0 = the
                     library's default rule)
 
@@ -51,7 +51,7 @@ SPLITS = (0, 1, 2, 4, 8, 12, 16, 24, 32, 48, 64, 128)
 def candidates(N: int):
     """(ipt, ws, nsplit); nsplit 0 is the library's default rule for that N."""
     Ns = N - 1
-    for ipt, ws in itertools.product((1, 2), (1, 4)):
+    for ipt, ws in itertools.product((1, 2), (1, 4, 8)):
         for ns in SPLITS:
             if ns <= 1 or ns <= max(1, Ns // (4 * ws)):
                 yield ipt, ws, ns

@@ -78,14 +78,14 @@ Shape pick_shape(int Ns, int precision) {
   }
   if (const char* env = getenv("PN_SHAPE")) {
     int a = 0, b = 0, c = 0;
-    if (sscanf(env, "%d,%d,%d", &a, &b, &c) == 3 && (a == 1 || a == 2) && (b == 1 || b == 4) &&
-        c >= 0) {
+    if (sscanf(env, "%d,%d,%d", &a, &b, &c) == 3 && (a == 1 || a == 2) &&
+        (b == 1 || b == 4 || b == 8) && c >= 0) {
       s.ipt = a;
       s.ws = b;
       want_nsplit = c;
     }
   }
-  const int ib = kBlock / s.ws * s.ipt;  // i-bodies per workgroup
+  const int ib = (s.ws == 1 ? kBlock : 64) * s.ipt;  // i-bodies per workgroup
   s.iblocks = (Ns + ib - 1) / ib;
   if (want_nsplit <= 0) {
     // default: about 4096 sweep workgroups, but at least 16 j per wavefront
@@ -393,7 +393,12 @@ int launch_prologue(const Sys& s, const Ptrs& P, int precision, hipStream_t st,
 template <typename T, int MODE>
 void launch_pair_t(const PairArgs& a, const Shape& sh, hipStream_t st) {
   dim3 grid(sh.iblocks, sh.nsplit);
-  if (sh.ws == 4) {
+  if (sh.ws == 8) {
+    if (sh.ipt == 2)
+      hipLaunchKernelGGL((k_pair<T, MODE, 2, 8>), grid, dim3(2 * kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_pair<T, MODE, 1, 8>), grid, dim3(2 * kBlock), 0, st, a);
+  } else if (sh.ws == 4) {
     if (sh.ipt == 2)
       hipLaunchKernelGGL((k_pair<T, MODE, 2, 4>), grid, dim3(kBlock), 0, st, a);
     else
@@ -580,7 +585,12 @@ int launch_bh_final(const EpiArgs& a, hipStream_t st) {
 template <typename T>
 void launch_pair_bh_t(const PairArgs& a, const EpiArgs& e, const Shape& sh, hipStream_t st) {
   dim3 grid(sh.iblocks + 1, sh.nsplit);
-  if (sh.ws == 4) {
+  if (sh.ws == 8) {
+    if (sh.ipt == 2)
+      hipLaunchKernelGGL((k_pair_bh<T, MODE_FUSED, 2, 8>), grid, dim3(2 * kBlock), 0, st, a, e);
+    else
+      hipLaunchKernelGGL((k_pair_bh<T, MODE_FUSED, 1, 8>), grid, dim3(2 * kBlock), 0, st, a, e);
+  } else if (sh.ws == 4) {
     if (sh.ipt == 2)
       hipLaunchKernelGGL((k_pair_bh<T, MODE_FUSED, 2, 4>), grid, dim3(kBlock), 0, st, a, e);
     else
@@ -1718,7 +1728,7 @@ int pn_set_shape(int precision, int64_t n_min, int64_t n_max, int ipt, int ws, i
     return PN_OK;
   }
   if ((precision != PN_FP64 && precision != PN_MIXED) || n_min < 2 || n_max < n_min ||
-      (ipt != 1 && ipt != 2) || (ws != 1 && ws != 4) || nsplit < 0 || nsplit > 65535)
+      (ipt != 1 && ipt != 2) || (ws != 1 && ws != 4 && ws != 8) || nsplit < 0 || nsplit > 65535)
     return PN_EINVAL;
   g_tuned.push_back(TunedShape{precision, n_min, n_max, ipt, ws, nsplit});
   return PN_OK;

@@ -623,10 +623,18 @@ __device__ __forceinline__ bool field_written(int f, int mode) {
   return (mode & MODE_P2) != 0;
 }
 
-// LDS of pair_block's wavefront reduction: WS - 1 waves park their sums.
+// Threads of a sweep workgroup: WS wavefronts sharing one i-range of 64 IPT
+// lanes (WS = 4 or 8), or 256 lanes (WS = 1).
+template <int WS>
+constexpr int pair_threads() {
+  return WS == 8 ? 2 * kBlock : kBlock;
+}
+
+// LDS of pair_block's wavefront reduction: WS = 4, waves 1-3 park their sums;
+// WS = 8, waves 4-7 then waves 1-3 (the same four regions).
 template <typename T, int IPT, int WS>
 constexpr int pair_red_doubles() {
-  return WS > 1 ? (WS - 1) * kNF * Width<T>::n * IPT * 64 : 1;
+  return WS > 1 ? (WS == 8 ? 4 : WS - 1) * kNF * Width<T>::n * IPT * 64 : 1;
 }
 
 // red: pair_red_doubles<T, IPT, WS>() doubles of LDS
@@ -634,7 +642,8 @@ template <typename T, int MODE, int IPT, int WS>
 __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp, double* red) {
   using Pk = typename PkOf<T>::type;
   constexpr int NFO = kNF * Width<T>::n;  // output fields per star
-  constexpr int LANES = kBlock / WS;  // distinct i-lanes per workgroup
+  static_assert(WS == 1 || WS == 4 || WS == 8, "wavefronts per i-range");
+  constexpr int LANES = pair_threads<WS>() / WS;  // distinct i-lanes per workgroup
   constexpr int IB = LANES * IPT;     // i-bodies per workgroup
   const Pk* __restrict__ pk = static_cast<const Pk*>(a.pk);
   const int wave = WS > 1 ? wave_id() : 0;
@@ -700,8 +709,27 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp, do
   } else {
     // fixed-order reduction over the WS wavefronts: waves 1..WS-1 park their
     // sums in LDS, wave 0 adds them to its own in wave order and stores
-    // (LDS of WS-1 waves only, so it does not cap the occupancy)
-    if (wave > 0) {
+    // (LDS of WS-1 waves only, so it does not cap the occupancy).  WS = 8:
+    // first wave w < 4 adds wave w + 4's sums to its own.
+    if constexpr (WS == 8) {
+      if (wave >= 4) {
+#pragma unroll
+        for (int f = 0; f < NFO; ++f)
+#pragma unroll
+          for (int ii = 0; ii < IPT; ++ii)
+            red[(((wave - 4) * NFO + f) * IPT + ii) * 64 + lane] = acc[f][ii];
+      }
+      __syncthreads();
+      if (wave < 4) {
+#pragma unroll
+        for (int f = 0; f < NFO; ++f)
+#pragma unroll
+          for (int ii = 0; ii < IPT; ++ii)
+            acc[f][ii] += red[((wave * NFO + f) * IPT + ii) * 64 + lane];
+      }
+      __syncthreads();
+    }
+    if (wave > 0 && wave < 4) {
 #pragma unroll
       for (int f = 0; f < NFO; ++f)
 #pragma unroll
@@ -719,7 +747,7 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp, do
             if (field_written(f, MODE)) {
               double sum = acc[f][ii];
 #pragma unroll
-              for (int w = 1; w < WS; ++w) sum += red[(((w - 1) * NFO + f) * IPT + ii) * 64 + lane];
+              for (int w = 1; w < 4; ++w) sum += red[(((w - 1) * NFO + f) * IPT + ii) * 64 + lane];
               out[f * plane + idx] = sum;
             }
           }
@@ -730,7 +758,7 @@ __device__ __forceinline__ void pair_block(const PairArgs& a, int ib, int sp, do
 }
 
 template <typename T, int MODE, int IPT, int WS>
-__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
+__global__ __launch_bounds__(pair_threads<WS>()) void k_pair(PairArgs a) {
   __shared__ double red[pair_red_doubles<T, IPT, WS>()];
   pair_block<T, MODE, IPT, WS>(a, blockIdx.x, blockIdx.y, red);
 }
@@ -1319,7 +1347,7 @@ __global__ __launch_bounds__(kBlock) void k_epilogue_dual_bh(EpiArgs a, EpiArgs 
 // sweep's (iblocks + 1) x nsplit; column iblocks, split 0 runs the update
 // (sharing the sweep's LDS), the rest of that column exits.
 template <typename T, int MODE, int IPT, int WS>
-__global__ __launch_bounds__(kBlock) void k_pair_bh(PairArgs a, EpiArgs e) {
+__global__ __launch_bounds__(pair_threads<WS>()) void k_pair_bh(PairArgs a, EpiArgs e) {
   constexpr int L = pair_red_doubles<T, IPT, WS>() > 7 * kBlock ? pair_red_doubles<T, IPT, WS>()
                                                                 : 7 * kBlock;
   __shared__ double lds[L];

@@ -83,6 +83,7 @@ def test_validation_without_device(lib):
     assert lib.pn_accel_eih(d, d, d, 16, 1.0, 30.0, 0.0, 5, d, d, d, None, 0) == EINVAL
     assert lib.pn_set_shape(0, 10, 5, 1, 4, 0) == EINVAL
     assert lib.pn_set_shape(0, 2, 5, 3, 4, 0) == EINVAL
+    assert lib.pn_set_shape(0, 2, 5, 1, 2, 0) == EINVAL  # wavefronts per i-range: 1, 4 or 8
     assert lib.pn_diagnostics(d, d, d, 16, 1.0, 30.0, 0.0, None, None, 0) == EINVAL
     assert lib.pn_encounters(d, d, d, 2, 1.0, 30.0, 0.1, d, None, 0) == EINVAL
     assert lib.pn_encounters(d, d, d, 16, 1.0, 30.0, -0.1, d, None, 0) == EINVAL
@@ -235,12 +236,19 @@ def test_query_shape_follows_the_tuned_table(lib):
         N = e["measured_N"]
         ipt, ws, nsplit, iblocks = _binding.pn_query_shape(prec, N)
         assert (ipt, ws) == (e["ipt"], e["ws"])
-        assert iblocks == -(-(N - 1) // (256 // ws * ipt))
+        assert iblocks == -(-(N - 1) // ((256 if ws == 1 else 64) * ipt))
         if e["nsplit"] > 0:  # the split count rounds through the j-chunk size
             Ns = N - 1
             want = max(1, min(e["nsplit"], Ns))
             jchunk = -(-Ns // want)
             assert nsplit == -(-Ns // jchunk)
+    # eight wavefronts per i-range: i-blocks of 64 lanes, as with four
+    _binding.pn_set_shape(-1, 0, 0, 0, 0, 0)
+    _binding.pn_set_shape(0, 2, 1 << 28, 2, 8, 12)
+    try:
+        assert tuple(_binding.pn_query_shape(0, 16384)) == (2, 8, 12, 128)
+    finally:
+        _binding.install_tuned_shapes()
     EINVAL = -1
     out = (ctypes.c_int * 4)()
     assert lib.pn_query_shape(0, 1, ctypes.cast(out, ctypes.c_void_p)) == EINVAL

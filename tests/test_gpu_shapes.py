@@ -1,5 +1,5 @@
 """Every launch shape of the sweep, forced with pn_set_shape: 1 or 2 i-bodies
-per lane, 1 or 4 wavefronts per i-range, the default or an odd split count,
+per lane, 1, 4 or 8 wavefronts per i-range, the default or an odd split count,
 in both precisions.  Each shape runs one evaluation (pn_accel: k_pair) and
 three RK4 steps (pn_step: the chained k_epilogue_chain / k_pair_bh sequence)
 on a ragged N = 1000 system, against the oracle; in FP64 also the two-pass
@@ -25,7 +25,7 @@ torch = pytest.importorskip("torch")
 
 G = 1.0
 N, M_BH, C, EPS, DT = 1000, 0.1, 30.0, 1e-4, 1e-4
-SHAPES = [(ipt, ws, ns) for ipt in (1, 2) for ws in (1, 4) for ns in (0, 3)]
+SHAPES = [(ipt, ws, ns) for ipt in (1, 2) for ws in (1, 4, 8) for ns in (0, 3)]
 
 
 @pytest.fixture(scope="module")
