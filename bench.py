@@ -51,10 +51,10 @@ PEAK_FP32_VALU = 157.3e12
 # Keyed by (workload, kernel, j-splits): the launch shape comes from the tuned
 # table, so a figure applies only to the kernel and split count it was taken on.
 TRAFFIC_BYTES = {
-    # FETCH 6356.73 KiB, WRITE 34582.1 KiB per launch
-    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,4>", 24): 48430653,
-    # FETCH 79974.3 KiB, WRITE 188669 KiB per launch
-    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,4>", 32): 356984422,
+    # FETCH 7233.07 KiB, WRITE 17291.1 KiB per launch
+    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,8>", 12): 32519414,
+    # FETCH 49328.6 KiB, WRITE 94334.7 KiB per launch
+    ("plummer_n65536_mixed", "k_pair_bh<float,3,1,8>", 16): 197623706,
 }
 
 
