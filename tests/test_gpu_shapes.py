@@ -99,3 +99,48 @@ def test_every_shape(pn, system, shape, prec):
         assert e <= 1e-12 and dp <= 1e-12 and dv <= 1e-12
     else:
         assert e <= 1e-6 and dp <= 1e-8 and dv <= 1e-6
+
+
+TINY = [(n, s) for n in (3, 17, 70) for s in ((1, 8, 1), (2, 8, 1), (1, 8, 0), (2, 4, 1))]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("n,shape", TINY, ids=[f"n{n}_ipt{a}_ws{b}_ns{c}" for n, (a, b, c) in TINY])
+def test_tiny_systems_in_wide_shapes(pn, n, shape, prec):
+    """Systems smaller than a workgroup's i-range and j-ranges shorter than
+    its wavefronts (some wavefronts get no j at all) in the 8-wavefront
+    shapes: one evaluation and three RK4 steps against the oracle."""
+    from paper_1801_07986_amd import _binding
+
+    pos, vel, mass = inputs.plummer_bh(n, M_BH, 920 + n)
+    rN, rphi, r1 = oracle.accel(pos, vel, mass, G, C, EPS)
+    rp, rv = oracle.step(pos, vel, mass, G, C, EPS, DT, 3)
+    d = pos[:, None, :] - pos[None, :, :]
+    R2 = (d * d).sum(-1) + EPS * EPS
+    np.fill_diagonal(R2, np.inf)
+    scale = (G * mass[None, :] / R2).sum(1)
+    print(f"[case] N={n} shape {shape} precision {prec}", flush=True)
+    pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
+    pn.pn_set_stage_kernel(-1, 0, 0, 0)
+    pn.pn_set_shape(prec, 2, 1 << 30, *shape)
+    try:
+        assert tuple(pn.pn_query_shape(prec, n)[:2]) == shape[:2]
+        aN = torch.empty((n, 3), dtype=torch.float64, device="cuda:0")
+        a1 = torch.empty_like(aN)
+        phi = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        pn.pn_accel(dev(pos), dev(vel), dev(mass), G, C, EPS, prec, aN, phi, a1)
+        P, V = dev(pos), dev(vel)
+        pn.pn_step(P, V, dev(mass), G, C, EPS, DT, 3, prec)
+    finally:
+        pn.pn_set_shape(-1, 0, 0, 0, 0, 0)
+        _binding.install_tuned_shapes()
+    e = rel(aN.cpu().numpy() + a1.cpu().numpy(), rN + r1, scale, 1e-3 if prec == 0 else 0.5)
+    ephi = (np.abs(phi.cpu().numpy() - rphi) / np.abs(rphi)).max()
+    gp, gv = P.cpu().numpy(), V.cpu().numpy()
+    dp = np.abs(gp - rp).max() / np.abs(rp).max()
+    dv = (np.linalg.norm(gv - rv, axis=1) / np.linalg.norm(rv, axis=1).max()).max()
+    print(f"N={n} {shape}: evaluation {e:.2e}, phi {ephi:.2e}, three steps: x {dp:.2e}, v {dv:.2e}")
+    if prec == 0:
+        assert e <= 1e-12 and ephi <= 1e-12 and dp <= 1e-12 and dv <= 1e-12
+    else:
+        assert e <= 1e-6 and ephi <= 1e-6 and dp <= 1e-8 and dv <= 1e-6
