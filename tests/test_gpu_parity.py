@@ -454,3 +454,26 @@ def test_async_calls_on_two_streams_do_not_interfere(pn):
     torch.cuda.synchronize()
     assert np.array_equal(host(PA), alone[0][0]) and np.array_equal(host(VA), alone[0][1])
     assert np.array_equal(host(PB), alone[1][0]) and np.array_equal(host(VB), alone[1][1])
+
+
+def test_async_long_runs_on_two_streams(pn):
+    """As above with runs long enough for the 16-step graph (each call
+    re-captures both graphs, since the two systems alternate): each system
+    ends exactly as when stepped alone for the same 60 steps."""
+    a = case(3000, 33)
+    b = case(2000, 34)
+    alone = []
+    for pos, vel, mass in (a, b):
+        P, V = dev(pos), dev(vel)
+        pn.pn_step(P, V, dev(mass), G, 30.0, 1e-4, 1e-4, 60, 0)
+        alone.append((host(P), host(V)))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    PA, VA, MA = dev(a[0]), dev(a[1]), dev(a[2])
+    PB, VB, MB = dev(b[0]), dev(b[1]), dev(b[2])
+    torch.cuda.synchronize()
+    for n in (20, 40):
+        pn.pn_step(PA, VA, MA, G, 30.0, 1e-4, 1e-4, n, 0, stream=s1, flags=pn.PN_ASYNC)
+        pn.pn_step(PB, VB, MB, G, 30.0, 1e-4, 1e-4, n, 0, stream=s2, flags=pn.PN_ASYNC)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(PA), alone[0][0]) and np.array_equal(host(VA), alone[0][1])
+    assert np.array_equal(host(PB), alone[1][0]) and np.array_equal(host(VB), alone[1][1])
