@@ -979,23 +979,23 @@ int capture_steps(DevState& d, int steps, Enqueue& enqueue_step, hipGraph_t* gra
 }
 
 // Replays the captured time step nsteps times on `st`: kStepsPerGraph steps
-// per launch of the long graph, the rest one per launch.  Each graph is
-// captured when first needed for this key (a new key drops both).  The steps
-// and their order are those of direct launches, so are the results.
+// per launch of the long graph, the rest one per launch.  Both graphs are
+// captured on the first call for a key (a new key drops both), so that a
+// short warm-up call leaves a long run nothing to capture.  The steps and
+// their order are those of direct launches, so are the results.
 template <typename Enqueue>
 int replay_step(DevState& d, const GraphKey& key, int64_t nsteps, hipStream_t st,
                 Enqueue enqueue_step) {
   if (!(key == d.key)) drop_graph(d);
   const int64_t nlong = nsteps / kStepsPerGraph, nshort = nsteps % kStepsPerGraph;
   int rc;
-  if (nlong > 0 && !d.gexec_k) {
+  if (!d.gexec_k) {
     if ((rc = capture_steps(d, kStepsPerGraph, enqueue_step, &d.graph_k, &d.gexec_k))) return rc;
-    d.key = key;
   }
-  if (nshort > 0 && !d.gexec) {
+  if (!d.gexec) {
     if ((rc = capture_steps(d, 1, enqueue_step, &d.graph, &d.gexec))) return rc;
-    d.key = key;
   }
+  d.key = key;
   for (int64_t k = 0; k < nlong; ++k) HIPCK(hipGraphLaunch(d.gexec_k, st));
   for (int64_t k = 0; k < nshort; ++k) HIPCK(hipGraphLaunch(d.gexec, st));
   return PN_OK;
