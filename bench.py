@@ -51,8 +51,8 @@ PEAK_FP32_VALU = 157.3e12
 # Keyed by (workload, kernel, j-splits): the launch shape comes from the tuned
 # table, so a figure applies only to the kernel and split count it was taken on.
 TRAFFIC_BYTES = {
-    # FETCH 7233.07 KiB, WRITE 17291.1 KiB per launch
-    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,8>", 12): 32519414,
+    # FETCH 7288.77 KiB, WRITE 17291.1 KiB per launch
+    ("plummer_n16384_fp64", "k_pair_bh<double,3,2,8>", 12): 32633487,
     # FETCH 49328.6 KiB, WRITE 94334.7 KiB per launch
     ("plummer_n65536_mixed", "k_pair_bh<float,3,1,8>", 16): 197623706,
 }

@@ -555,6 +555,20 @@ __device__ __forceinline__ void pair_range(const typename PkOf<T>::type* __restr
                                            PairAcc<T, IPT>& A) {
   using Pk = typename PkOf<T>::type;
   int j = j0;
+  // FP64: four j per iteration (the same order of additions, 1-2 % faster
+  // than two); FP32 keeps two, where four cost occupancy
+  if constexpr (sizeof(T) == 8) {
+    for (; j + 3 < j1; j += 4) {
+      const Pk p0 = pk[j];
+      const Pk p1 = pk[j + 1];
+      const Pk p2 = pk[j + 2];
+      const Pk p3 = pk[j + 3];
+      pair_one<T, MODE, IPT, MASK>(p0, j, eps2, I, A);
+      pair_one<T, MODE, IPT, MASK>(p1, j + 1, eps2, I, A);
+      pair_one<T, MODE, IPT, MASK>(p2, j + 2, eps2, I, A);
+      pair_one<T, MODE, IPT, MASK>(p3, j + 3, eps2, I, A);
+    }
+  }
   // two j per iteration: two independent dependency chains per wavefront
   for (; j + 1 < j1; j += 2) {
     const Pk p0 = pk[j];
