@@ -31,7 +31,11 @@ stars per workgroup against the chained two-kernel stages in their tuned
 shape; the sizes where a one-launch stage wins become "stage" entries of the
 same table (installed with pn_set_stage_kernel).
 
-Usage (on the GPU):  python -m paper_1801_07986_amd.autotune [--out PATH] [--quick | --batched | --stage]
+With --sizes N,... and/or --precision fp64|mixed it re-tunes only those sizes
+and/or that precision and keeps the table's other entries.
+
+Usage (on the GPU):  python -m paper_1801_07986_amd.autotune [--out PATH]
+                     [--quick | --batched | --stage | --sizes N,...] [--precision fp64|mixed]
 """
 from __future__ import annotations
 
@@ -79,7 +83,10 @@ def time_step(pn, torch, P, V, Mm, prec, budget_s=0.05, reps=3):
     return best
 
 
-def tune(sizes, log=print):
+PRECISIONS = ("fp64", "mixed")
+
+
+def tune(sizes, log=print, precisions=PRECISIONS):
     import torch
 
     import paper_1801_07986_amd as pn
@@ -95,6 +102,8 @@ def tune(sizes, log=print):
         V = torch.from_numpy(vel).cuda()
         Mm = torch.from_numpy(mass).cuda()
         for prec_name, prec in (("fp64", pn.PN_FP64), ("mixed", pn.PN_MIXED)):
+            if prec_name not in precisions:
+                continue
             best = None
             for ipt, ws, ns in candidates(N):
                 os.environ["PN_SHAPE"] = f"{ipt},{ws},{ns}"
@@ -239,6 +248,8 @@ def main(argv=None):
     ap.add_argument("--sizes", default=None,
                     help="comma-separated N: re-tune these sizes only, keeping the table's "
                          "other entries (ranges are recomputed over all measured sizes)")
+    ap.add_argument("--precision", choices=PRECISIONS, default=None,
+                    help="re-tune this precision only, keeping the other's entries")
     ap.add_argument("--batched", action="store_true",
                     help="tune pn_step_batched's shape only (kept with the existing table)")
     ap.add_argument("--stage", action="store_true",
@@ -258,15 +269,22 @@ def main(argv=None):
         table["stage"] = tune_stage(log=log)
         table["stage_created"] = time.strftime("%Y-%m-%d %H:%M:%S")
     else:
+        precs = (args.precision,) if args.precision else PRECISIONS
         if args.sizes:
             sizes = sorted({int(s) for s in args.sizes.split(",")})
+        else:
+            sizes = QUICK_SIZES if args.quick else SIZES
+        if args.sizes or args.precision:
+            # an entry is re-measured only if both its size and its precision are
             kept = [dict(N=e["measured_N"], precision=e["precision"], ipt=e["ipt"], ws=e["ws"],
                          nsplit=e["nsplit"], step_ms=e["step_ms"],
                          default_step_ms=e["default_step_ms"])
-                    for e in old.get("entries", []) if e["measured_N"] not in sizes]
-            table = to_table(kept + tune(sizes, log=log))
+                    for e in old.get("entries", [])
+                    if not (e["measured_N"] in sizes and e["precision"] in precs)
+                    and (args.sizes or e["precision"] not in precs)]
+            table = to_table(kept + tune(sizes, log=log, precisions=precs))
         else:
-            table = to_table(tune(QUICK_SIZES if args.quick else SIZES, log=log))
+            table = to_table(tune(sizes, log=log))
         for key in ("batched", "stage"):
             if key in old:
                 table[key] = old[key]

@@ -302,9 +302,9 @@ def test_autotune_partial_retune_keeps_other_entries(tmp_path, monkeypatch):
     out = tmp_path / "t.json"
     out.write_text(json.dumps(old))
 
-    def fake_tune(sizes, log=print):
+    def fake_tune(sizes, log=print, precisions=("fp64", "mixed")):
         return [dict(N=N, precision=p, ipt=2, ws=1, nsplit=7, step_ms=1.0, default_step_ms=2.0)
-                for N in sizes for p in ("fp64", "mixed")]
+                for N in sizes for p in precisions]
 
     monkeypatch.setattr(autotune, "tune", fake_tune)
     autotune.main(["--sizes", "1024,5000", "--out", str(out)])
@@ -322,5 +322,52 @@ def test_autotune_partial_retune_keeps_other_entries(tmp_path, monkeypatch):
                 o = next(x for x in e_old if x["measured_N"] == e["measured_N"])
                 assert (e["ipt"], e["ws"], e["nsplit"]) == (o["ipt"], o["ws"], o["nsplit"])
         # ranges tile [2, 2^28] without gaps or overlaps
+        assert e_new[0]["n_min"] == 2 and e_new[-1]["n_max"] == 1 << 28
+        assert all(a["n_max"] + 1 == b["n_min"] for a, b in zip(e_new, e_new[1:]))
+
+
+def test_autotune_one_precision_keeps_the_other(tmp_path, monkeypatch):
+    """autotune --precision: only that precision's entries are re-measured
+    (at --sizes, or over the whole ladder); the other precision's table is
+    kept unchanged (host logic; the timing is replaced by a stub)."""
+    import json
+
+    from paper_1801_07986_amd import autotune
+
+    src = os.path.join(ROOT, "paper_1801_07986_amd", "tuned_shapes.json")
+    with open(src) as f:
+        old = json.load(f)
+    asked = []
+
+    def fake_tune(sizes, log=print, precisions=("fp64", "mixed")):
+        asked.append((list(sizes), tuple(precisions)))
+        return [dict(N=N, precision=p, ipt=2, ws=1, nsplit=7, step_ms=1.0, default_step_ms=2.0)
+                for N in sizes for p in precisions]
+
+    monkeypatch.setattr(autotune, "tune", fake_tune)
+    shape = lambda e: (e["measured_N"], e["ipt"], e["ws"], e["nsplit"])  # noqa: E731
+    by_prec = lambda t, p: [shape(e) for e in t["entries"] if e["precision"] == p]  # noqa: E731
+
+    out = tmp_path / "a.json"
+    out.write_text(json.dumps(old))
+    autotune.main(["--sizes", "65536,131072", "--precision", "fp64", "--out", str(out)])
+    new = json.loads(out.read_text())
+    assert asked[-1] == ([65536, 131072], ("fp64",))
+    assert by_prec(new, "mixed") == by_prec(old, "mixed")
+    assert new["stage"] == old["stage"] and new["batched"] == old["batched"]
+    for n, ipt, ws, ns in by_prec(new, "fp64"):
+        o = next(x for x in by_prec(old, "fp64") if x[0] == n)
+        assert (ipt, ws, ns) == ((2, 1, 7) if n in (65536, 131072) else o[1:])
+    assert len(by_prec(new, "fp64")) == len(by_prec(old, "fp64"))
+
+    out = tmp_path / "b.json"
+    out.write_text(json.dumps(old))
+    autotune.main(["--precision", "mixed", "--quick", "--out", str(out)])
+    new = json.loads(out.read_text())
+    assert asked[-1] == (autotune.QUICK_SIZES, ("mixed",))
+    assert by_prec(new, "fp64") == by_prec(old, "fp64")
+    assert by_prec(new, "mixed") == [(n, 2, 1, 7) for n in autotune.QUICK_SIZES]
+    for prec in ("fp64", "mixed"):
+        e_new = [e for e in new["entries"] if e["precision"] == prec]
         assert e_new[0]["n_min"] == 2 and e_new[-1]["n_max"] == 1 << 28
         assert all(a["n_max"] + 1 == b["n_min"] for a, b in zip(e_new, e_new[1:]))
